@@ -1,0 +1,147 @@
+"""Throughput of the per-pixel X-ray tracing sum on one MI355X.
+
+One step = one full-size shot: 2463 x 2527 pixels x 2^2 sub-pixels x 3 sensor
+layers x 100 sources x 50 mosaic domains = 3.7344e11 pixel terms, binary64,
+inputs (tables, structure factors) resident on the device; the step is the
+xrt_simulate call (small table upload + the spots kernel).  The same shot is
+also timed in the mixed-precision form and its error against the oracle on
+sampled pixels is reported beside it.
+
+Prints one JSON line.  Synthetic, seeded inputs (synth.full_shot).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Lane-issue slots of the binary64 / mixed inner term (sincg), counted from
+# the operation list of the spots kernel: fixed before tuning.  A slot is one
+# wave64 lane-op at full rate; transcendentals (rcp) count 4.
+C_ALG = {"fp64": 115, "mixed": 98}
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz
+PEAK_SLOTS = 256 * 64 * 2.4e9
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_form(shot, fh, precision, steps, warmup):
+    import torch
+    from paper_2205_07976_amd import xrt
+    out = torch.empty(shot.roi_shape, dtype=torch.float64 if precision == "fp64" else torch.float32,
+                      device="cuda")
+    for _ in range(warmup):
+        xrt.simulate(shot, fh, precision=precision, out=out)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        xrt.simulate(shot, fh, precision=precision, out=out)
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = [a.elapsed_time(b) for a, b in evs]
+    return out, wall, ev_ms
+
+
+def cpu_baseline(shot, budget_s=15.0):
+    """The oracle on a seeded pixel subset sized to about budget_s seconds."""
+    import synth
+    from oracle import oracle as o
+    cores = min(16, os.cpu_count() or 1)
+    n = 64
+    while True:
+        pix = synth.pixel_sample(shot, n, 99)
+        t0 = time.perf_counter()
+        o.simulate(shot, pix, nthreads=cores)
+        dt = time.perf_counter() - t0
+        if dt >= budget_s / 4 or n >= 65536:
+            break
+        n = min(65536, int(n * max(2.0, budget_s / max(dt, 1e-3) / 2)))
+    terms = n * shot.terms_per_pixel
+    return {"value": terms / dt / 1e9, "unit": "Gterm/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} seeded pixels of the full-size shot ({terms:.3e} terms, {dt:.1f} s)"}
+
+
+def mixed_error(shot, img32):
+    import numpy as np
+    import synth
+    from oracle import oracle as o
+    pix = synth.pixel_sample(shot, 256, 2024)
+    ref = o.simulate(shot, pix, nthreads=min(16, os.cpu_count() or 1))
+    x = img32[pix[:, 1], pix[:, 0]].astype(np.float64)
+    r = np.abs(x - ref) / ref
+    return float(r.max()), float(np.sqrt(np.mean(r * r)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); shots would be sharded "
+              "one per GPU with no exchange, which this build does not launch.", file=sys.stderr)
+        return 2
+
+    import torch
+    import synth
+    from paper_2205_07976_amd import xrt
+
+    torch.cuda.set_device(0)
+    shot = synth.full_shot()
+    fh = xrt.Fhkl.from_shot(shot)
+    terms = shot.n_terms
+    log(f"full-size shot: {terms:.4e} terms; fp64 warmup {args.warmup} steps {args.steps}")
+
+    img64, wall, ev = time_form(shot, fh, "fp64", args.steps, args.warmup)
+    ms = 1e3 * wall / args.steps
+    kern_ms = sum(ev) / len(ev)
+    value = terms / (wall / args.steps) / 1e9
+    ach = C_ALG["fp64"] * terms / (kern_ms * 1e-3)
+    res = {
+        "metric": "pixel-term evaluations/s (G/s) vs FP32 VALU peak; p50/p99 shot latency",
+        "value": value, "unit": "Gterm/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "full-size shot, binary64: 2463x2527 px, oversample 2, 3 layers, "
+                               "100 sources, 50 mosaic domains, sincg N=20, Fhkl [-60,60]^3",
+                   "pixels": shot.n_pixels, "terms_per_pixel": shot.terms_per_pixel, "terms": terms},
+        "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_SLOTS / 1e12,
+                     "unit": "Tlane-op/s", "frac": ach / PEAK_SLOTS, "traffic": None,
+                     "kernel": "spots_kernel<FP64,SINCG>", "kernel_ms": kern_ms,
+                     "c_alg_slots_per_term": C_ALG["fp64"]},
+    }
+    log(f"fp64: {ms:.1f} ms/step (events {kern_ms:.1f} ms), {value:.1f} Gterm/s, "
+        f"roofline frac {ach / PEAK_SLOTS:.3f}")
+
+    if not args.no_mixed:
+        img32, wall32, ev32 = time_form(shot, fh, "mixed", args.steps, args.warmup)
+        k32 = sum(ev32) / len(ev32)
+        v32 = terms / (wall32 / args.steps) / 1e9
+        a32 = C_ALG["mixed"] * terms / (k32 * 1e-3)
+        emax, erms = mixed_error(shot, img32.cpu().numpy())
+        res["mixed"] = {"value": v32, "unit": "Gterm/s", "ms_per_step": 1e3 * wall32 / args.steps,
+                        "kernel_ms": k32, "frac": a32 / PEAK_SLOTS, "speedup_vs_fp64": v32 / value,
+                        "max_rel_err": emax, "rms_rel_err": erms, "err_sample": "256 seeded pixels"}
+        log(f"mixed: {1e3 * wall32 / args.steps:.1f} ms/step, {v32:.1f} Gterm/s, max rel err {emax:.2e}")
+
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(shot)
+        log(f"cpu oracle: {res['cpu_baseline']}")
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,194 @@
+/*
+ * xrt.h -- C ABI of the MI355X X-ray tracing library (libxrt.so).
+ *
+ * The library simulates crystal diffraction images pixel by pixel, as the
+ * spots kernel of "Accelerating X-Ray Tracing for Exascale Systems using
+ * Kokkos" (section III) does: every pixel of a detector is formed from a
+ * physical model of the crystal -- its orientation, its mosaic domains, the
+ * photon energy spectrum and one structure factor per Bragg spot (section II,
+ * "Scientific background") -- and pixels are independent (section III).
+ *
+ * For pixel (i_f, i_s) the library computes, in the kinematic model,
+ *
+ *   I = r_e^2 * fluence * scale / (O^2 * n_phi * n_mos)
+ *       * sum_{u,v < O} sum_{t < n_layers}  dOmega * capture_t
+ *         * sum_{j < n_src}  w_j * P_j
+ *           * sum_{k < n_phi} sum_{m < n_mos}  F(h0)^2 * L^2(h - h0)
+ *
+ *   sample point  r = Fp fdet + Sp sdet + (distance + t*layer_dt) odet,
+ *                 Fp = (i_f + (v + 1/2)/O) pixel - beam_f  (Sp likewise, u)
+ *   direction     d = r/|r|; dOmega = pixel^2 (d.odet)/|r|^2
+ *   capture_t     exp(-t dt/(mu d.odet)) - exp(-(t+1) dt/(mu d.odet)), or 1
+ *                 when layer_dt == 0 (Beer-Lambert)
+ *   scattering    S = (d - dir_j)/lambda_j            (1/angstrom)
+ *   polarization  P_j = (1 + cos^2 2theta - K cos 2psi sin^2 2theta)/2
+ *                 (Kahn et al. 1982; psi measured from the part of evec
+ *                 perpendicular to dir_j)
+ *   Miller index  h = M_{k,m} S, rows of M_{k,m} = umat_m R(spindle, phi0 +
+ *                 k dphi) U {a, b, c}; h0 = nearest integer (ties to even)
+ *   lattice       SINCG: prod_i sin^2(pi N_i f_i)/sin^2(pi f_i), f = h - h0
+ *                 (limit N_i^2 at f_i = 0); GAUSS: prod_i N_i^2 exp(-2 N_i^2
+ *                 f_i^2 / gauss_c)
+ *   F(h0)         the table entry, or F_default outside the table.
+ *
+ * Conventions
+ *  - Units: metres (detector), angstrom (wavelengths, cell), radians.
+ *  - Arrays are row-major.  Images are [roi_s1-roi_s0][roi_f1-roi_f0], the
+ *    fast index contiguous.
+ *  - Every call returns an xrt_status: 0 on success, a negative code
+ *    otherwise; xrt_last_error() then holds a message (per thread).
+ *  - Validation errors are returned before anything is enqueued.  A device
+ *    fault is reported as XRT_EDEVICE by the call that sees it.
+ *  - Work is enqueued on the caller's HIP stream (a hipStream_t passed as
+ *    void*; NULL is the default stream) and is complete when that stream is.
+ *  - Every struct starts with struct_size = sizeof(struct); a smaller value
+ *    from an older caller is rejected with XRT_EVERSION.
+ *  - Host arrays named in a struct (sources, mosaic rotations) are read
+ *    during the call only; the caller may free them when it returns.
+ *  - Device pointers (structure-factor values, images) stay owned by the
+ *    caller and must stay valid until the stream reaches the work.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef XRT_H
+#define XRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XRT_VERSION_MAJOR 1
+#define XRT_VERSION_MINOR 0
+
+typedef int32_t xrt_status;
+enum {
+    XRT_OK = 0,
+    XRT_EINVAL = -1,   /* an argument is malformed (NaN, negative size, ...) */
+    XRT_ERANGE = -2,   /* a size exceeds what the library supports */
+    XRT_ENOMEM = -3,   /* a device or host allocation failed */
+    XRT_EDEVICE = -4,  /* the HIP runtime reported an error */
+    XRT_EBUSY = -5,    /* the object is in use */
+    XRT_EVERSION = -6  /* struct_size does not match this library */
+};
+
+enum { XRT_SHAPE_SINCG = 0, XRT_SHAPE_GAUSS = 1 };
+
+/* Arithmetic of the sum.
+ * XRT_FP64:  every step in IEEE binary64.
+ * XRT_MIXED: sample-point geometry, S, h and the reduced arguments f and
+ *            N f - rint(N f) in binary64; lattice factor, structure factor and
+ *            products in binary32; per-pixel sums compensated (Kahan) in
+ *            binary32. */
+enum { XRT_FP64 = 0, XRT_MIXED = 1 };
+
+enum { XRT_F32 = 0, XRT_F64 = 1 };
+
+typedef struct xrt_detector {
+    uint32_t struct_size;
+    int32_t n_fast, n_slow;        /* detector size, pixels (>= 1) */
+    double pixel;                  /* pixel pitch, m (> 0) */
+    double distance;               /* sample to front face along odet, m (> 0) */
+    double beam_f, beam_s;         /* position of the detector origin's offset:
+                                      the point Fp = Sp = 0, m */
+    double fdet[3], sdet[3], odet[3]; /* fast, slow axes and normal (unit) */
+    int32_t oversample;            /* O >= 1 sub-pixels per axis */
+    int32_t n_layers;              /* sensor layers >= 1 */
+    double layer_dt;               /* layer thickness, m (>= 0; 0 => n_layers 1) */
+    double atten_len;              /* attenuation length mu, m (> 0) */
+    int32_t roi_f0, roi_f1, roi_s0, roi_s1; /* half-open region of interest */
+} xrt_detector;
+
+typedef struct xrt_beam {
+    uint32_t struct_size;
+    int32_t n_src;                 /* sources >= 1 */
+    const double *dir;             /* host [n_src][3] unit propagation directions */
+    const double *lambda;          /* host [n_src] wavelengths, angstrom (> 0) */
+    const double *weight;          /* host [n_src] weights (finite) */
+    double fluence;                /* photons / m^2 */
+    double kahn;                   /* polarization factor K */
+    double evec[3];                /* polarization direction (unit, not along
+                                      any dir_j) */
+} xrt_beam;
+
+typedef struct xrt_crystal {
+    uint32_t struct_size;
+    double cell[9];                /* rows a, b, c in the crystal frame, angstrom */
+    double U[9];                   /* orientation (crystal -> lab) */
+    int32_t n_mos;                 /* mosaic domains >= 1 */
+    const double *umats;           /* host [n_mos][3][3] domain rotations (lab) */
+    int32_t n_phi;                 /* spindle steps >= 1 */
+    double phi0, dphi;             /* spindle angles, rad */
+    double spindle[3];             /* spindle axis (unit) */
+    double N[3];                   /* unit cells along a, b, c: SINCG integers in
+                                      [1, 1000]; GAUSS reals in (0, 1000] */
+    int32_t shape;                 /* XRT_SHAPE_* */
+    double gauss_c;                /* Gaussian width constant (> 0) */
+    double scale;                  /* overall scale s */
+} xrt_crystal;
+
+typedef struct xrt_fhkl_desc {
+    uint32_t struct_size;
+    int32_t hkl_min[3];            /* first tabulated h, k, l (|.| <= 2^20) */
+    int32_t hkl_count[3];          /* entries per axis, >= 1, product < 2^28 */
+    int32_t dtype;                 /* XRT_F32 or XRT_F64: type of the values */
+    double F_default;              /* structure factor outside the table */
+} xrt_fhkl_desc;
+
+/* Opaque structure-factor table resident on one device. */
+typedef struct xrt_fhkl xrt_fhkl;
+
+/* Library version (XRT_VERSION_MAJOR / MINOR of the built library). */
+xrt_status xrt_version(int32_t *major, int32_t *minor);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *xrt_last_error(void);
+
+/* Structure factors of a crystal (section II: one real structure factor per
+ * Bragg spot), made resident on the current device.
+ *  dev_F   device pointer to hkl_count[0]*hkl_count[1]*hkl_count[2] values of
+ *          type desc->dtype, l fastest.  Read on `stream` before the call
+ *          returns (the call synchronises the stream); the caller keeps it.
+ *  out     receives a handle owning a padded copy of F^2 in binary64 and
+ *          binary32; free it with xrt_fhkl_destroy.
+ * Errors: EINVAL (NULL pointers, bad dtype, NaN default), ERANGE (sizes),
+ *         ENOMEM, EDEVICE. */
+xrt_status xrt_fhkl_create(const xrt_fhkl_desc *desc, const void *dev_F, void *stream,
+                           xrt_fhkl **out);
+
+/* Release a table.  The caller must make sure no enqueued work still uses it
+ * (synchronise the streams it was used on).  NULL is accepted. */
+xrt_status xrt_fhkl_destroy(xrt_fhkl *fhkl);
+
+/* Simulate the region of interest of one shot (section III, the spots
+ * kernel: crystal orientation, mosaicity and photon energy).
+ *  precision   XRT_FP64 or XRT_MIXED.
+ *  dev_image   device pointer, [roi rows][roi cols] of out_dtype.
+ *  accumulate  0: the image is overwritten; 1: the new values are added to it
+ *              in out_dtype (the separate add-image kernel of section III,
+ *              fused into the store).
+ * The call uploads a few small tables (cell matrices, sources) stream-ordered
+ * and launches one kernel on `stream`.
+ * Errors: EINVAL / ERANGE on any malformed field, ENOMEM, EDEVICE. */
+xrt_status xrt_simulate(const xrt_detector *det, const xrt_beam *beam,
+                        const xrt_crystal *xtal, const xrt_fhkl *fhkl,
+                        int32_t precision, void *dev_image, int32_t out_dtype,
+                        int32_t accumulate, void *stream);
+
+/* Diagnostics: the library's lab-frame cell matrices M_{k,m} (host output,
+ * [n_phi*n_mos][3][3], rows a', b', c'), exactly as the kernels receive them. */
+xrt_status xrt_cell_mats(const xrt_crystal *xtal, double *host_out);
+
+/* Diagnostics: S and h of n single terms, computed on the device by the same
+ * code as the binary64 kernel.  host_idx: [n][6] int32 sextuples (i_f, i_s,
+ * u*O + v, t, j, k*n_mos + m); host_S, host_h: [n][3] binary64 outputs.
+ * Synchronous (the call waits for the device).
+ * Errors: EINVAL/ERANGE on malformed shots or indices, ENOMEM, EDEVICE. */
+xrt_status xrt_trace_terms(const xrt_detector *det, const xrt_beam *beam,
+                           const xrt_crystal *xtal, int64_t n,
+                           const int32_t *host_idx, double *host_S, double *host_h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XRT_H */

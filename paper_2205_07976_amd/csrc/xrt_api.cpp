@@ -1,0 +1,427 @@
+// xrt_api.cpp -- host side of libxrt: the C ABI of include/xrt.h.
+//
+// Validates every argument, builds the per-shot tables (lab-frame cell
+// matrices, sources with their polarization basis) in binary64, uploads them
+// stream-ordered and launches the kernels.  Compiled with -ffp-contract=off:
+// the cell matrices follow the fixed operation sequence documented at
+// build_cell_mats so that h is reproducible bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/xrt.h"
+#include "xrt_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+xrt_status fail(xrt_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+xrt_status fail(xrt_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+xrt_status hip_fail(hipError_t e, const char *what)
+{
+    if (e == hipErrorOutOfMemory)
+        return fail(XRT_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(XRT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                      \
+    do {                                         \
+        hipError_t e_ = (call);                  \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+constexpr double R_E = 2.8179403262e-15;  // classical electron radius, m (CODATA 2018)
+constexpr double UNIT_TOL = 1e-12;
+constexpr int32_t MAX_LOOP = 1 << 20;
+
+bool is_fin(double x) { return std::isfinite(x); }
+bool is_fin_n(const double *x, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(x[i])) return false;
+    return true;
+}
+double dot3(const double *a, const double *b) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+bool unit3(const double *a) { return is_fin_n(a, 3) && std::fabs(std::sqrt(dot3(a, a)) - 1.0) <= UNIT_TOL; }
+
+xrt_status check_detector(const xrt_detector *d)
+{
+    if (!d) return fail(XRT_EINVAL, "detector is NULL");
+    if (d->struct_size != sizeof(xrt_detector))
+        return fail(XRT_EVERSION, "xrt_detector.struct_size %u, library expects %zu", d->struct_size,
+                    sizeof(xrt_detector));
+    if (d->n_fast < 1 || d->n_slow < 1) return fail(XRT_EINVAL, "detector size must be >= 1");
+    if ((int64_t)d->n_fast * d->n_slow >= (int64_t)1 << 31)
+        return fail(XRT_ERANGE, "detector has 2^31 or more pixels");
+    if (!is_fin(d->pixel) || d->pixel <= 0) return fail(XRT_EINVAL, "pixel must be finite and > 0");
+    if (!is_fin(d->distance) || d->distance <= 0) return fail(XRT_EINVAL, "distance must be finite and > 0");
+    if (!is_fin(d->beam_f) || !is_fin(d->beam_s)) return fail(XRT_EINVAL, "beam centre must be finite");
+    if (!unit3(d->fdet) || !unit3(d->sdet) || !unit3(d->odet))
+        return fail(XRT_EINVAL, "fdet, sdet and odet must be unit vectors");
+    if (d->oversample < 1 || d->oversample > 64) return fail(XRT_ERANGE, "oversample must be in [1, 64]");
+    if (d->n_layers < 1 || d->n_layers > 64) return fail(XRT_ERANGE, "n_layers must be in [1, 64]");
+    if (!is_fin(d->layer_dt) || d->layer_dt < 0) return fail(XRT_EINVAL, "layer_dt must be finite and >= 0");
+    if (d->layer_dt == 0 && d->n_layers != 1)
+        return fail(XRT_EINVAL, "layer_dt == 0 (no thickness model) requires n_layers == 1");
+    if (!is_fin(d->atten_len) || d->atten_len <= 0) return fail(XRT_EINVAL, "atten_len must be finite and > 0");
+    if (d->roi_f0 < 0 || d->roi_f1 > d->n_fast || d->roi_f0 >= d->roi_f1 || d->roi_s0 < 0 ||
+        d->roi_s1 > d->n_slow || d->roi_s0 >= d->roi_s1)
+        return fail(XRT_EINVAL, "ROI [%d,%d)x[%d,%d) is empty or outside the %dx%d detector", d->roi_f0,
+                    d->roi_f1, d->roi_s0, d->roi_s1, d->n_fast, d->n_slow);
+    return XRT_OK;
+}
+
+xrt_status check_beam(const xrt_beam *b)
+{
+    if (!b) return fail(XRT_EINVAL, "beam is NULL");
+    if (b->struct_size != sizeof(xrt_beam))
+        return fail(XRT_EVERSION, "xrt_beam.struct_size %u, library expects %zu", b->struct_size,
+                    sizeof(xrt_beam));
+    if (b->n_src < 1 || b->n_src > MAX_LOOP) return fail(XRT_ERANGE, "n_src must be in [1, 2^20]");
+    if (!b->dir || !b->lambda || !b->weight) return fail(XRT_EINVAL, "source arrays must not be NULL");
+    if (!is_fin(b->fluence) || !is_fin(b->kahn)) return fail(XRT_EINVAL, "fluence and kahn must be finite");
+    if (!unit3(b->evec)) return fail(XRT_EINVAL, "evec must be a unit vector");
+    for (int j = 0; j < b->n_src; ++j) {
+        const double *d = b->dir + 3 * j;
+        if (!unit3(d)) return fail(XRT_EINVAL, "source %d: direction is not a unit vector", j);
+        if (!is_fin(b->lambda[j]) || b->lambda[j] <= 0)
+            return fail(XRT_EINVAL, "source %d: lambda must be finite and > 0", j);
+        if (!is_fin(b->weight[j])) return fail(XRT_EINVAL, "source %d: weight must be finite", j);
+        if (std::fabs(dot3(d, b->evec)) > 1.0 - 1e-6)
+            return fail(XRT_EINVAL, "source %d: evec is parallel to the source direction", j);
+    }
+    return XRT_OK;
+}
+
+xrt_status check_crystal(const xrt_crystal *x)
+{
+    if (!x) return fail(XRT_EINVAL, "crystal is NULL");
+    if (x->struct_size != sizeof(xrt_crystal))
+        return fail(XRT_EVERSION, "xrt_crystal.struct_size %u, library expects %zu", x->struct_size,
+                    sizeof(xrt_crystal));
+    if (!is_fin_n(x->cell, 9) || !is_fin_n(x->U, 9)) return fail(XRT_EINVAL, "cell and U must be finite");
+    if (x->n_mos < 1 || x->n_phi < 1) return fail(XRT_EINVAL, "n_mos and n_phi must be >= 1");
+    if ((int64_t)x->n_mos * x->n_phi > MAX_LOOP) return fail(XRT_ERANGE, "n_phi * n_mos exceeds 2^20");
+    if (!x->umats) return fail(XRT_EINVAL, "umats must not be NULL");
+    if (!is_fin_n(x->umats, 9 * (size_t)x->n_mos)) return fail(XRT_EINVAL, "umats must be finite");
+    if (!is_fin(x->phi0) || !is_fin(x->dphi)) return fail(XRT_EINVAL, "phi0 and dphi must be finite");
+    if (!unit3(x->spindle)) return fail(XRT_EINVAL, "spindle must be a unit vector");
+    if (x->shape != XRT_SHAPE_SINCG && x->shape != XRT_SHAPE_GAUSS)
+        return fail(XRT_EINVAL, "unknown shape %d", x->shape);
+    for (int i = 0; i < 3; ++i) {
+        const double N = x->N[i];
+        if (!is_fin(N) || N <= 0 || N > 1000) return fail(XRT_ERANGE, "N[%d] must be in (0, 1000]", i);
+        if (x->shape == XRT_SHAPE_SINCG && N != std::floor(N))
+            return fail(XRT_EINVAL, "N[%d] = %g: the sincg shape needs whole unit cells", i, N);
+    }
+    if (!is_fin(x->gauss_c) || x->gauss_c <= 0) return fail(XRT_EINVAL, "gauss_c must be finite and > 0");
+    if (!is_fin(x->scale)) return fail(XRT_EINVAL, "scale must be finite");
+    return XRT_OK;
+}
+
+void matvec(const double *Q, const double *x, double *y)
+{
+    for (int r = 0; r < 3; ++r) y[r] = (Q[3 * r + 0] * x[0] + Q[3 * r + 1] * x[1]) + Q[3 * r + 2] * x[2];
+}
+
+// Rotation by phi about the unit axis u (Rodrigues), entry by entry as
+// (((1 - c) u_r) u_q + [r == q] c) + s K_rq with K the cross-product matrix.
+void rodrigues(const double *u, double phi, double *R)
+{
+    const double c = std::cos(phi), s = std::sin(phi);
+    const double K[9] = {0.0, -u[2], u[1], u[2], 0.0, -u[0], -u[1], u[0], 0.0};
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q)
+            R[3 * r + q] = (((1.0 - c) * u[r]) * u[q] + (r == q ? c : 0.0)) + s * K[3 * r + q];
+}
+
+// Lab-frame cell matrices M_{k,m}, rows a'_i = umat_m (R_k (U a_i)), each
+// product y_r = (Q_r0 x_0 + Q_r1 x_1) + Q_r2 x_2 (paper section II: the
+// crystal orientation and its mosaic domains).
+void build_cell_mats(const xrt_crystal *x, double *out)
+{
+    for (int k = 0; k < x->n_phi; ++k) {
+        double Rk[9];
+        rodrigues(x->spindle, x->phi0 + (double)k * x->dphi, Rk);
+        for (int m = 0; m < x->n_mos; ++m) {
+            double *M = out + 9 * ((size_t)k * x->n_mos + m);
+            for (int i = 0; i < 3; ++i) {
+                double v1[3], v2[3];
+                matvec(x->U, x->cell + 3 * i, v1);
+                matvec(Rk, v1, v2);
+                matvec(x->umats + 9 * (size_t)m, v2, M + 3 * i);
+            }
+        }
+    }
+}
+
+// Source rows: direction, wavelength, weight and the polarization basis
+// e_perp = unit(evec - (evec . dir) dir), b = dir x e_perp.
+void build_sources(const xrt_beam *b, double *out)
+{
+    for (int j = 0; j < b->n_src; ++j) {
+        double *row = out + xrt::SRC_STRIDE * (size_t)j;
+        const double *d = b->dir + 3 * j;
+        std::memset(row, 0, sizeof(double) * xrt::SRC_STRIDE);
+        for (int i = 0; i < 3; ++i) row[xrt::SRC_DIR + i] = d[i];
+        row[xrt::SRC_LAMBDA] = b->lambda[j];
+        row[xrt::SRC_WEIGHT] = b->weight[j];
+        const double ed = dot3(b->evec, d);
+        double e[3];
+        for (int i = 0; i < 3; ++i) e[i] = b->evec[i] - ed * d[i];
+        const double n = std::sqrt(dot3(e, e));
+        for (int i = 0; i < 3; ++i) e[i] /= n;
+        row[xrt::SRC_E + 0] = e[0];
+        row[xrt::SRC_E + 1] = e[1];
+        row[xrt::SRC_E + 2] = e[2];
+        row[xrt::SRC_B + 0] = d[1] * e[2] - d[2] * e[1];
+        row[xrt::SRC_B + 1] = d[2] * e[0] - d[0] * e[2];
+        row[xrt::SRC_B + 2] = d[0] * e[1] - d[1] * e[0];
+    }
+}
+
+// Geometry and lattice fields of the kernel parameters (everything except
+// tables and output).
+void fill_params(const xrt_detector *d, const xrt_beam *b, const xrt_crystal *x, xrt::Params &p)
+{
+    std::memset(&p, 0, sizeof p);
+    p.pixel = d->pixel;
+    p.distance = d->distance;
+    p.beam_f = d->beam_f;
+    p.beam_s = d->beam_s;
+    for (int i = 0; i < 3; ++i) {
+        p.fdet[i] = d->fdet[i];
+        p.sdet[i] = d->sdet[i];
+        p.odet[i] = d->odet[i];
+    }
+    p.layer_dt = d->layer_dt;
+    p.atten_len = d->atten_len;
+    p.O = d->oversample;
+    p.T = d->n_layers;
+    p.roi_f0 = d->roi_f0;
+    p.roi_s0 = d->roi_s0;
+    p.roi_nf = d->roi_f1 - d->roi_f0;
+    p.roi_ns = d->roi_s1 - d->roi_s0;
+    p.tiles_f = (p.roi_nf + 15) / 16;
+    p.n_tiles = p.tiles_f * ((p.roi_ns + 15) / 16);
+    p.n_src = b->n_src;
+    p.n_rot = x->n_phi * x->n_mos;
+    p.shape = x->shape;
+    double ln = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        p.N[i] = x->N[i];
+        p.gk[i] = 2.0 * x->N[i] * x->N[i] / x->gauss_c;
+        ln += 2.0 * std::log(x->N[i]);
+    }
+    p.ln_n2 = ln;
+    p.kahn = b->kahn;
+    const double O = (double)d->oversample;
+    p.norm = R_E * R_E * b->fluence * x->scale / (O * O * (double)x->n_phi * (double)x->n_mos);
+}
+
+}  // namespace
+
+struct xrt_fhkl {
+    int device;
+    int32_t lo[3], hi[3];
+    int32_t sa, sb;
+    double *F2_64;
+    float *F2_32;
+};
+
+extern "C" {
+
+xrt_status xrt_version(int32_t *major, int32_t *minor)
+{
+    if (!major || !minor) return fail(XRT_EINVAL, "NULL output pointer");
+    *major = XRT_VERSION_MAJOR;
+    *minor = XRT_VERSION_MINOR;
+    return XRT_OK;
+}
+
+const char *xrt_last_error(void) { return g_err.c_str(); }
+
+xrt_status xrt_fhkl_create(const xrt_fhkl_desc *desc, const void *dev_F, void *stream, xrt_fhkl **out)
+{
+    if (!desc || !dev_F || !out) return fail(XRT_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (desc->struct_size != sizeof(xrt_fhkl_desc))
+        return fail(XRT_EVERSION, "xrt_fhkl_desc.struct_size %u, library expects %zu", desc->struct_size,
+                    sizeof(xrt_fhkl_desc));
+    if (desc->dtype != XRT_F32 && desc->dtype != XRT_F64) return fail(XRT_EINVAL, "dtype must be XRT_F32 or XRT_F64");
+    if (!is_fin(desc->F_default)) return fail(XRT_EINVAL, "F_default must be finite");
+    int64_t padded = 1;
+    for (int i = 0; i < 3; ++i) {
+        if (desc->hkl_count[i] < 1) return fail(XRT_EINVAL, "hkl_count[%d] must be >= 1", i);
+        if (desc->hkl_min[i] < -(1 << 20) || desc->hkl_min[i] > (1 << 20) ||
+            (int64_t)desc->hkl_min[i] + desc->hkl_count[i] > (1 << 20))
+            return fail(XRT_ERANGE, "axis %d: table must lie within |h| <= 2^20", i);
+        padded *= (int64_t)desc->hkl_count[i] + 2;
+    }
+    if (padded >= (int64_t)1 << 28) return fail(XRT_ERANGE, "padded table has 2^28 or more entries");
+    const int64_t sb = (int64_t)desc->hkl_count[2] + 2;
+    const int64_t sa = ((int64_t)desc->hkl_count[1] + 2) * sb;
+    if (sa >= (1 << 24)) return fail(XRT_ERANGE, "(nk+2)*(nl+2) must be below 2^24");
+
+    xrt_fhkl *t = new (std::nothrow) xrt_fhkl();
+    if (!t) return fail(XRT_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&t->device);
+    if (e == hipSuccess) e = hipMalloc((void **)&t->F2_64, sizeof(double) * padded);
+    if (e == hipSuccess) e = hipMalloc((void **)&t->F2_32, sizeof(float) * padded);
+    hipStream_t s = (hipStream_t)stream;
+    if (e == hipSuccess)
+        e = xrt::launch_pad_table(dev_F, desc->dtype == XRT_F64, desc->hkl_count[0], desc->hkl_count[1],
+                                  desc->hkl_count[2], desc->F_default, t->F2_64, t->F2_32, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(t->F2_64);
+        (void)hipFree(t->F2_32);
+        delete t;
+        return hip_fail(e, "xrt_fhkl_create");
+    }
+    for (int i = 0; i < 3; ++i) {
+        t->lo[i] = desc->hkl_min[i] - 1;
+        t->hi[i] = desc->hkl_min[i] + desc->hkl_count[i];
+    }
+    t->sa = (int32_t)sa;
+    t->sb = (int32_t)sb;
+    *out = t;
+    return XRT_OK;
+}
+
+xrt_status xrt_fhkl_destroy(xrt_fhkl *t)
+{
+    if (!t) return XRT_OK;
+    hipError_t e1 = hipFree(t->F2_64);
+    hipError_t e2 = hipFree(t->F2_32);
+    delete t;
+    if (e1 != hipSuccess) return hip_fail(e1, "xrt_fhkl_destroy");
+    if (e2 != hipSuccess) return hip_fail(e2, "xrt_fhkl_destroy");
+    return XRT_OK;
+}
+
+xrt_status xrt_cell_mats(const xrt_crystal *xtal, double *host_out)
+{
+    xrt_status st = check_crystal(xtal);
+    if (st) return st;
+    if (!host_out) return fail(XRT_EINVAL, "NULL output pointer");
+    build_cell_mats(xtal, host_out);
+    return XRT_OK;
+}
+
+xrt_status xrt_simulate(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal,
+                        const xrt_fhkl *fhkl, int32_t precision, void *dev_image, int32_t out_dtype,
+                        int32_t accumulate, void *stream)
+{
+    xrt_status st;
+    if ((st = check_detector(det)) || (st = check_beam(beam)) || (st = check_crystal(xtal))) return st;
+    if (!fhkl) return fail(XRT_EINVAL, "fhkl is NULL");
+    if (precision != XRT_FP64 && precision != XRT_MIXED) return fail(XRT_EINVAL, "unknown precision %d", precision);
+    if (out_dtype != XRT_F32 && out_dtype != XRT_F64) return fail(XRT_EINVAL, "unknown out_dtype %d", out_dtype);
+    if (accumulate != 0 && accumulate != 1) return fail(XRT_EINVAL, "accumulate must be 0 or 1");
+    if (!dev_image) return fail(XRT_EINVAL, "dev_image is NULL");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != fhkl->device)
+        return fail(XRT_EINVAL, "fhkl lives on device %d, current device is %d", fhkl->device, dev);
+
+    const size_t n_rot = (size_t)xtal->n_phi * xtal->n_mos;
+    const size_t n_words = 9 * n_rot + xrt::SRC_STRIDE * (size_t)beam->n_src;
+    std::vector<double> host(n_words);
+    build_cell_mats(xtal, host.data());
+    build_sources(beam, host.data() + 9 * n_rot);
+
+    xrt::Params p;
+    fill_params(det, beam, xtal, p);
+    p.F2_64 = fhkl->F2_64;
+    p.F2_32 = fhkl->F2_32;
+    for (int i = 0; i < 3; ++i) {
+        p.lo[i] = fhkl->lo[i];
+        p.hi[i] = fhkl->hi[i];
+    }
+    p.sa = fhkl->sa;
+    p.sb = fhkl->sb;
+    p.image = dev_image;
+    p.out_f64 = out_dtype == XRT_F64;
+    p.accumulate = accumulate;
+
+    hipStream_t s = (hipStream_t)stream;
+    double *tables = nullptr;
+    HIP_TRY(hipMallocAsync((void **)&tables, sizeof(double) * n_words, s), "hipMallocAsync");
+    hipError_t e = hipMemcpyAsync(tables, host.data(), sizeof(double) * n_words, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        p.mats = tables;
+        p.src = tables + 9 * n_rot;
+        e = xrt::launch_spots(p, precision, s);
+    }
+    hipError_t e2 = hipFreeAsync(tables, s);
+    if (e != hipSuccess) return hip_fail(e, "xrt_simulate");
+    if (e2 != hipSuccess) return hip_fail(e2, "xrt_simulate: hipFreeAsync");
+    return XRT_OK;
+}
+
+xrt_status xrt_trace_terms(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal,
+                           int64_t n, const int32_t *host_idx, double *host_S, double *host_h)
+{
+    xrt_status st;
+    if ((st = check_detector(det)) || (st = check_beam(beam)) || (st = check_crystal(xtal))) return st;
+    if (n < 0 || n > (1 << 24)) return fail(XRT_ERANGE, "n must be in [0, 2^24]");
+    if (n == 0) return XRT_OK;
+    if (!host_idx || !host_S || !host_h) return fail(XRT_EINVAL, "NULL array");
+    const int O = det->oversample, nrot = xtal->n_phi * xtal->n_mos;
+    for (int64_t q = 0; q < n; ++q) {
+        const int32_t *e = host_idx + 6 * q;
+        if (e[0] < 0 || e[0] >= det->n_fast || e[1] < 0 || e[1] >= det->n_slow || e[2] < 0 ||
+            e[2] >= O * O || e[3] < 0 || e[3] >= det->n_layers || e[4] < 0 || e[4] >= beam->n_src ||
+            e[5] < 0 || e[5] >= nrot)
+            return fail(XRT_ERANGE, "term %lld: index out of range", (long long)q);
+    }
+    const size_t n_rot = (size_t)nrot;
+    const size_t n_words = 9 * n_rot + xrt::SRC_STRIDE * (size_t)beam->n_src;
+    std::vector<double> host(n_words);
+    build_cell_mats(xtal, host.data());
+    build_sources(beam, host.data() + 9 * n_rot);
+    xrt::Params p;
+    fill_params(det, beam, xtal, p);
+
+    double *tables = nullptr, *dS = nullptr, *dh = nullptr;
+    int32_t *didx = nullptr;
+    hipError_t e = hipMalloc((void **)&tables, sizeof(double) * n_words);
+    if (e == hipSuccess) e = hipMalloc((void **)&dS, sizeof(double) * 3 * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&dh, sizeof(double) * 3 * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&didx, sizeof(int32_t) * 6 * n);
+    if (e == hipSuccess) e = hipMemcpy(tables, host.data(), sizeof(double) * n_words, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(didx, host_idx, sizeof(int32_t) * 6 * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        p.mats = tables;
+        p.src = tables + 9 * n_rot;
+        e = xrt::launch_trace(p, n, didx, dS, dh, nullptr);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(host_S, dS, sizeof(double) * 3 * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(host_h, dh, sizeof(double) * 3 * n, hipMemcpyDeviceToHost);
+    (void)hipFree(tables);
+    (void)hipFree(dS);
+    (void)hipFree(dh);
+    (void)hipFree(didx);
+    if (e != hipSuccess) return hip_fail(e, "xrt_trace_terms");
+    return XRT_OK;
+}
+
+}  // extern "C"

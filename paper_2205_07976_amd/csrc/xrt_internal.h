@@ -1,0 +1,64 @@
+// xrt_internal.h -- structures shared by the host side and the kernels of
+// libxrt.  Not part of the public ABI (that is include/xrt.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/xrt.h"
+
+namespace xrt {
+
+// Per-source table row: propagation direction, wavelength, weight, and the
+// polarization basis (e_perp, dir x e_perp) in which the azimuth psi is
+// measured.  Padded to 12 doubles (96 B) so a row is two aligned scalar loads.
+constexpr int SRC_STRIDE = 12;
+enum { SRC_DIR = 0, SRC_LAMBDA = 3, SRC_WEIGHT = 4, SRC_E = 5, SRC_B = 8 };
+
+// Lower bound of |f| = |h - rint(h)| inside the binary64/32 lattice factor.
+// sin^2(pi N f)/sin^2(pi f) = N^2 (1 - (N^2-1) pi^2 f^2 / 3 + ...), so for
+// |f| <= 2^-32 it equals N^2 to a relative 3.3 N^2 2^-64 (<= 1.8e-13 at the
+// largest accepted N = 1000, <= 3e-16 at N = 40); replacing such f by 2^-32
+// removes the 0/0 at f = 0 without a branch or select.
+constexpr double F_FLOOR = 2.3283064365386963e-10;  // 2^-32
+
+struct Params {
+    // detector and sample-point geometry (binary64)
+    double pixel, distance, beam_f, beam_s;
+    double fdet[3], sdet[3], odet[3];
+    double layer_dt, atten_len;
+    int32_t O, T;
+    int32_t roi_f0, roi_s0, roi_nf, roi_ns;
+    int32_t tiles_f, n_tiles;
+    // loop extents
+    int32_t n_src, n_rot;
+    // lattice
+    int32_t shape;
+    double N[3];
+    double gk[3];          // Gaussian: 2 N_i^2 / gauss_c
+    double ln_n2;          // Gaussian: log(prod N_i^2)
+    double kahn;
+    double norm;           // r_e^2 fluence scale / (O^2 n_phi n_mos)
+    // structure factors: padded tables of F^2, with one layer of F_default
+    // around the tabulated box
+    const double *F2_64;
+    const float *F2_32;
+    int32_t lo[3], hi[3];  // clamp range of h0 (hkl_min - 1, hkl_max + 1)
+    int32_t sa, sb;        // padded strides of the h and k axes
+    // per-shot tables in device memory
+    const double *mats;    // [n_rot][9]
+    const double *src;     // [n_src][SRC_STRIDE]
+    // output
+    void *image;
+    int32_t out_f64;
+    int32_t accumulate;
+};
+
+// Launchers (xrt_kernels.hip).  Return the hipError_t of the launch.
+hipError_t launch_spots(const Params &p, int precision, hipStream_t stream);
+hipError_t launch_pad_table(const void *src, int src_f64, int32_t na, int32_t nb, int32_t nc,
+                            double F_default, double *F2_64, float *F2_32, hipStream_t stream);
+hipError_t launch_trace(const Params &p, int64_t n, const int32_t *idx, double *S, double *h,
+                        hipStream_t stream);
+
+}  // namespace xrt

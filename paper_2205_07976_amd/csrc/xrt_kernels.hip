@@ -1,0 +1,325 @@
+// xrt_kernels.hip -- HIP kernels of libxrt for CDNA4 (gfx950).
+//
+// The spots kernel (paper section III: the kernel that forms the Bragg spots
+// from crystal orientation, mosaicity and photon energy) is a VALU-bound loop:
+// per pixel term it computes h = M S, the reduced arguments, six sinpi
+// polynomials, one division and one structure-factor gather, with no reuse
+// that a matrix core could exploit.  Layout decisions:
+//
+//  * one pixel per lane, 8 x 8 pixels per wave, 16 x 16 per 256-lane
+//    workgroup: neighbouring pixels have nearly equal h, so one gather of a
+//    wave touches a handful of table lines;
+//  * workgroup ids are remapped so that each of the 8 XCDs (dispatched
+//    round-robin) gets one contiguous band of tiles and keeps the part of the
+//    F^2 table its band needs in its own L2;
+//  * the per-shot tables (cell matrices, sources) are indexed by loop
+//    counters that are the same for the whole wave, so they are read with
+//    scalar loads into SGPRs;
+//  * loop order: sub-pixel and layer (geometry in binary64), source (S, P),
+//    then the inner loop over spindle steps and mosaic domains, which is the
+//    hot loop; the per-pixel result is stored once, coalesced per row.
+//
+// The file is compiled with -ffp-contract=off: S and h follow a fixed
+// operation sequence (below), and every fused multiply-add is explicit.
+#include "xrt_internal.h"
+#include "xrt_math.h"
+
+namespace xrt {
+
+constexpr int TILE = 16;  // pixels per tile edge
+constexpr int BLOCK = 256;
+
+// ---------------------------------------------------------------------------
+// Sample-point geometry, binary64, fixed operation order:
+//   Fp = ((double)i_f + ((double)v + 0.5) / O) * pixel - beam_f  (Sp likewise)
+//   r_i = (Fp fdet_i + Sp sdet_i) + (distance + t dt) odet_i
+//   R = sqrt((r0 r0 + r1 r1) + r2 r2);  d_i = r_i / R
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sample_dir(const Params &p, int i_f, int i_s, int u, int v, int t,
+                                           double d[3], double &R)
+{
+    const double O = (double)p.O;
+    const double Fp = ((double)i_f + ((double)v + 0.5) / O) * p.pixel - p.beam_f;
+    const double Sp = ((double)i_s + ((double)u + 0.5) / O) * p.pixel - p.beam_s;
+    const double L = p.distance + (double)t * p.layer_dt;
+    double r[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) r[i] = (Fp * p.fdet[i] + Sp * p.sdet[i]) + L * p.odet[i];
+    R = __builtin_sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) d[i] = r[i] / R;
+}
+
+// dOmega * capture of a sample point: solid angle of the full pixel area
+// (sub-pixels are averaged by the final 1/O^2) times the Beer-Lambert
+// fraction absorbed in layer t, written exp(-a) (1 - exp(-(b - a))) with
+// expm1 so that thin layers keep their relative accuracy.
+__device__ __forceinline__ double sample_weight(const Params &p, const double d[3], double R, int t)
+{
+    const double cosrho = (d[0] * p.odet[0] + d[1] * p.odet[1]) + d[2] * p.odet[2];
+    const double domega = p.pixel * p.pixel * cosrho / (R * R);
+    if (p.layer_dt == 0.0) return domega;
+    const double l = p.atten_len * cosrho;
+    return domega * exp(-(double)t * p.layer_dt / l) * -expm1(-p.layer_dt / l);
+}
+
+// S = (d - dir_j) / lambda_j, binary64.
+__device__ __forceinline__ void scatter(const double *src, const double d[3], double S[3])
+{
+    const double lam = src[SRC_LAMBDA];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) S[i] = (d[i] - src[SRC_DIR + i]) / lam;
+}
+
+// Kahn factor with x = d.e_perp, y = d.(dir x e_perp): for a unit d,
+// cos 2psi sin^2 2theta = x^2 - y^2, so P = (1 + c^2 - K (x^2 - y^2)) / 2.
+__device__ __forceinline__ double polarization(const double *src, const double d[3], double K)
+{
+    const double c = (d[0] * src[SRC_DIR] + d[1] * src[SRC_DIR + 1]) + d[2] * src[SRC_DIR + 2];
+    const double x = (d[0] * src[SRC_E] + d[1] * src[SRC_E + 1]) + d[2] * src[SRC_E + 2];
+    const double y = (d[0] * src[SRC_B] + d[1] * src[SRC_B + 1]) + d[2] * src[SRC_B + 2];
+    return 0.5 * (1.0 + c * c - K * (x * x - y * y));
+}
+
+// h_i = fma(M_i2, S_2, M_i0 S_0 + M_i1 S_1)
+__device__ __forceinline__ void miller(const double *M, const double S[3], double h[3])
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        h[i] = __builtin_fma(M[3 * i + 2], S[2], M[3 * i] * S[0] + M[3 * i + 1] * S[1]);
+}
+
+// Index of the nearest reflection in the padded F^2 table.  Entries outside
+// the tabulated box clamp onto the border layer, which holds F_default^2.
+__device__ __forceinline__ int table_index(const Params &p, const double hr[3])
+{
+    int q[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        int v = (int)hr[i];  // v_cvt_i32_f64 saturates
+        v = v < p.lo[i] ? p.lo[i] : v;
+        v = v > p.hi[i] ? p.hi[i] : v;
+        q[i] = v - p.lo[i];
+    }
+    return __umul24(q[0], p.sa) + __umul24(q[1], p.sb) + q[2];
+}
+
+// ---------------------------------------------------------------------------
+// One term F^2 L^2, binary64.
+// ---------------------------------------------------------------------------
+template <int SHAPE>
+__device__ __forceinline__ double term_f64(const Params &p, const double h[3])
+{
+    double hr[3];
+    double L2;
+    if (SHAPE == XRT_SHAPE_SINCG) {
+        double num = 1.0, den = 1.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            hr[i] = __builtin_rint(h[i]);
+            const double fa = __builtin_fmax(__builtin_fabs(h[i] - hr[i]), F_FLOOR);
+            const double t = p.N[i] * fa;
+            const double g = t - __builtin_rint(t);
+            num *= g * sinpi_over_x(g * g);
+            den *= fa * sinpi_over_x(fa * fa);
+        }
+        const double q = num / den;
+        L2 = q * q;
+    } else {
+        double e = p.ln_n2;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            hr[i] = __builtin_rint(h[i]);
+            const double f = h[i] - hr[i];
+            e = __builtin_fma(-p.gk[i], f * f, e);
+        }
+        L2 = exp(e);
+    }
+    return p.F2_64[table_index(p, hr)] * L2;
+}
+
+// One term, mixed: h, f and g in binary64 (they decide the conditioning),
+// everything after the reduced arguments in binary32.
+template <int SHAPE>
+__device__ __forceinline__ float term_mixed(const Params &p, const double h[3])
+{
+    double hr[3];
+    float L2;
+    if (SHAPE == XRT_SHAPE_SINCG) {
+        float num = 1.0f, den = 1.0f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            hr[i] = __builtin_rint(h[i]);
+            const double fa = __builtin_fmax(__builtin_fabs(h[i] - hr[i]), F_FLOOR);
+            const double t = p.N[i] * fa;
+            const float g = (float)(t - __builtin_rint(t));
+            const float f = (float)fa;
+            num *= g * sinpi_over_x(g * g);
+            den *= f * sinpi_over_x(f * f);
+        }
+        const float q = num * __builtin_amdgcn_rcpf(den);
+        L2 = q * q;
+    } else {
+        double e = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            hr[i] = __builtin_rint(h[i]);
+            const double f = h[i] - hr[i];
+            e = __builtin_fma(-p.gk[i], f * f, e);
+        }
+        L2 = __expf((float)(e + p.ln_n2));
+    }
+    return p.F2_32[table_index(p, hr)] * L2;
+}
+
+__device__ __forceinline__ void kahn_add(float &s, float &c, float x)
+{
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// Workgroup id -> tile id: XCD x (workgroups x, x+8, x+16, ...) gets the
+// contiguous range of tiles [start(x), start(x) + count(x)).
+__device__ __forceinline__ int xcd_tile(int bid, int n_tiles)
+{
+    const int q = n_tiles >> 3, r = n_tiles & 7;
+    const int x = bid & 7, k = bid >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+template <int PREC, int SHAPE>
+__global__ __launch_bounds__(BLOCK) void spots_kernel(const Params p)
+{
+    const int tile = xcd_tile(blockIdx.x, p.n_tiles);
+    const int tf = tile % p.tiles_f, ts = tile / p.tiles_f;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lf = tf * TILE + (wave & 1) * 8 + (lane & 7);
+    const int ls = ts * TILE + (wave >> 1) * 8 + (lane >> 3);
+    const bool live = lf < p.roi_nf && ls < p.roi_ns;
+    // lanes past the ROI edge trace the last valid pixel and do not store
+    const int i_f = p.roi_f0 + (lf < p.roi_nf ? lf : p.roi_nf - 1);
+    const int i_s = p.roi_s0 + (ls < p.roi_ns ? ls : p.roi_ns - 1);
+
+    double acc64 = 0.0;
+    float acc = 0.0f, accc = 0.0f;
+    for (int u = 0; u < p.O; ++u)
+        for (int v = 0; v < p.O; ++v)
+            for (int t = 0; t < p.T; ++t) {
+                double d[3], R;
+                sample_dir(p, i_f, i_s, u, v, t, d, R);
+                const double wgeo = sample_weight(p, d, R, t);
+                for (int j = 0; j < p.n_src; ++j) {
+                    const double *src = p.src + SRC_STRIDE * j;
+                    double S[3];
+                    scatter(src, d, S);
+                    const double w = src[SRC_WEIGHT] * polarization(src, d, p.kahn) * wgeo;
+                    if (PREC == XRT_FP64) {
+                        double sub = 0.0;
+                        for (int r = 0; r < p.n_rot; ++r) {
+                            double h[3];
+                            miller(p.mats + 9 * r, S, h);
+                            sub += term_f64<SHAPE>(p, h);
+                        }
+                        acc64 = __builtin_fma(w, sub, acc64);
+                    } else {
+                        float s = 0.0f, c = 0.0f;
+                        for (int r = 0; r < p.n_rot; ++r) {
+                            double h[3];
+                            miller(p.mats + 9 * r, S, h);
+                            kahn_add(s, c, term_mixed<SHAPE>(p, h));
+                        }
+                        kahn_add(acc, accc, (float)w * (s - c));
+                    }
+                }
+            }
+    if (!live) return;
+    const double val = p.norm * (PREC == XRT_FP64 ? acc64 : (double)(acc - accc));
+    const size_t o = (size_t)ls * p.roi_nf + lf;
+    if (p.out_f64) {
+        double *img = (double *)p.image;
+        img[o] = p.accumulate ? img[o] + val : val;
+    } else {
+        float *img = (float *)p.image;
+        img[o] = p.accumulate ? img[o] + (float)val : (float)val;
+    }
+}
+
+hipError_t launch_spots(const Params &p, int precision, hipStream_t stream)
+{
+    dim3 grid(p.n_tiles), block(BLOCK);
+    if (precision == XRT_FP64) {
+        if (p.shape == XRT_SHAPE_SINCG)
+            hipLaunchKernelGGL((spots_kernel<XRT_FP64, XRT_SHAPE_SINCG>), grid, block, 0, stream, p);
+        else
+            hipLaunchKernelGGL((spots_kernel<XRT_FP64, XRT_SHAPE_GAUSS>), grid, block, 0, stream, p);
+    } else {
+        if (p.shape == XRT_SHAPE_SINCG)
+            hipLaunchKernelGGL((spots_kernel<XRT_MIXED, XRT_SHAPE_SINCG>), grid, block, 0, stream, p);
+        else
+            hipLaunchKernelGGL((spots_kernel<XRT_MIXED, XRT_SHAPE_GAUSS>), grid, block, 0, stream, p);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Padded F^2 tables: entry (a, b, c) of the (na+2)(nb+2)(nc+2) box holds
+// F(a-1, b-1, c-1)^2 inside and F_default^2 on the border layer.
+// ---------------------------------------------------------------------------
+__global__ void pad_table_kernel(const void *src, int src_f64, int na, int nb, int nc,
+                                 double F_default, double *F2_64, float *F2_32)
+{
+    const int pb = nb + 2, pc = nc + 2;
+    const int64_t total = (int64_t)(na + 2) * pb * pc;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % pc);
+        const int b = (int)((i / pc) % pb);
+        const int a = (int)(i / ((int64_t)pb * pc));
+        double F = F_default;
+        if (a >= 1 && a <= na && b >= 1 && b <= nb && c >= 1 && c <= nc) {
+            const int64_t s = ((int64_t)(a - 1) * nb + (b - 1)) * nc + (c - 1);
+            F = src_f64 ? ((const double *)src)[s] : (double)((const float *)src)[s];
+        }
+        F2_64[i] = F * F;
+        F2_32[i] = (float)(F * F);
+    }
+}
+
+hipError_t launch_pad_table(const void *src, int src_f64, int32_t na, int32_t nb, int32_t nc,
+                            double F_default, double *F2_64, float *F2_32, hipStream_t stream)
+{
+    hipLaunchKernelGGL(pad_table_kernel, dim3(1024), dim3(256), 0, stream, src, src_f64, na, nb,
+                       nc, F_default, F2_64, F2_32);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics: S and h of single terms by the code of the spots kernel.
+// ---------------------------------------------------------------------------
+__global__ void trace_kernel(const Params p, int64_t n, const int32_t *idx, double *S_out,
+                             double *h_out)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int32_t *e = idx + 6 * q;
+    double d[3], R, S[3], h[3];
+    sample_dir(p, e[0], e[1], e[2] / p.O, e[2] % p.O, e[3], d, R);
+    scatter(p.src + SRC_STRIDE * e[4], d, S);
+    miller(p.mats + 9 * e[5], S, h);
+    for (int i = 0; i < 3; ++i) {
+        S_out[3 * q + i] = S[i];
+        h_out[3 * q + i] = h[i];
+    }
+}
+
+hipError_t launch_trace(const Params &p, int64_t n, const int32_t *idx, double *S, double *h,
+                        hipStream_t stream)
+{
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(trace_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, n, idx, S, h);
+    return hipGetLastError();
+}
+
+}  // namespace xrt

@@ -1,0 +1,226 @@
+"""Python binding of libxrt (include/xrt.h): argument marshalling only.
+
+Every step of the tracing sum runs in the HIP library; this module converts
+a shot description (any object with the attribute names of ``synth.Shot``)
+into the C structs, passes torch device pointers and the current HIP stream,
+and turns status codes into exceptions.  It raises if libxrt.so is missing:
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxrt.so")
+
+XRT_OK, XRT_EINVAL, XRT_ERANGE, XRT_ENOMEM, XRT_EDEVICE, XRT_EBUSY, XRT_EVERSION = 0, -1, -2, -3, -4, -5, -6
+XRT_SHAPE_SINCG, XRT_SHAPE_GAUSS = 0, 1
+XRT_FP64, XRT_MIXED = 0, 1
+XRT_F32, XRT_F64 = 0, 1
+
+_d3 = C.c_double * 3
+_d9 = C.c_double * 9
+_i3 = C.c_int32 * 3
+_pd = C.POINTER(C.c_double)
+
+
+class Detector(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("n_fast", C.c_int32), ("n_slow", C.c_int32),
+        ("pixel", C.c_double), ("distance", C.c_double),
+        ("beam_f", C.c_double), ("beam_s", C.c_double),
+        ("fdet", _d3), ("sdet", _d3), ("odet", _d3),
+        ("oversample", C.c_int32), ("n_layers", C.c_int32),
+        ("layer_dt", C.c_double), ("atten_len", C.c_double),
+        ("roi_f0", C.c_int32), ("roi_f1", C.c_int32), ("roi_s0", C.c_int32), ("roi_s1", C.c_int32),
+    ]
+
+
+class Beam(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("n_src", C.c_int32),
+        ("dir", _pd), ("lam", _pd), ("weight", _pd),
+        ("fluence", C.c_double), ("kahn", C.c_double), ("evec", _d3),
+    ]
+
+
+class Crystal(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("cell", _d9), ("U", _d9),
+        ("n_mos", C.c_int32), ("umats", _pd),
+        ("n_phi", C.c_int32), ("phi0", C.c_double), ("dphi", C.c_double),
+        ("spindle", _d3), ("N", _d3), ("shape", C.c_int32),
+        ("gauss_c", C.c_double), ("scale", C.c_double),
+    ]
+
+
+class FhklDesc(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("hkl_min", _i3), ("hkl_count", _i3),
+        ("dtype", C.c_int32), ("F_default", C.c_double),
+    ]
+
+
+class XrtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"xrt error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+#: every entry point of include/xrt.h
+SYMBOLS = ("xrt_version", "xrt_last_error", "xrt_fhkl_create", "xrt_fhkl_destroy",
+           "xrt_simulate", "xrt_cell_mats", "xrt_trace_terms")
+
+
+def load():
+    """Load libxrt.so (built by ``paper_2205_07976_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2205_07976_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    lib.xrt_version.argtypes = [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.xrt_last_error.restype = C.c_char_p
+    lib.xrt_fhkl_create.argtypes = [C.POINTER(FhklDesc), C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.xrt_fhkl_destroy.argtypes = [C.c_void_p]
+    lib.xrt_simulate.argtypes = [C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal), C.c_void_p,
+                                 C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
+    lib.xrt_cell_mats.argtypes = [C.POINTER(Crystal), C.c_void_p]
+    lib.xrt_trace_terms.argtypes = [C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal), C.c_int64,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]
+    for name in SYMBOLS:
+        if name != "xrt_last_error":
+            getattr(lib, name).restype = C.c_int32
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != XRT_OK:
+        raise XrtError(rc, load().xrt_last_error().decode())
+
+
+def version():
+    a, b = C.c_int32(), C.c_int32()
+    _check(load().xrt_version(C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def _arr(x, dtype=np.float64):
+    return np.ascontiguousarray(np.asarray(x, dtype=dtype))
+
+
+class ShotStructs:
+    """The three C structs of one shot plus the host arrays they point to."""
+
+    def __init__(self, shot, roi=None):
+        f0, f1, s0, s1 = shot.roi if roi is None else roi
+        self.det = Detector(
+            C.sizeof(Detector), shot.n_fast, shot.n_slow, shot.pixel, shot.distance,
+            shot.beam_f, shot.beam_s, _d3(*shot.fdet), _d3(*shot.sdet), _d3(*shot.odet),
+            shot.oversample, shot.n_layers, shot.layer_dt, shot.atten_len, f0, f1, s0, s1)
+        self._keep = [_arr(shot.src_dir), _arr(shot.src_lambda), _arr(shot.src_weight), _arr(shot.umats)]
+        sd, sl, sw, um = self._keep
+        self.beam = Beam(C.sizeof(Beam), len(sl), sd.ctypes.data_as(_pd), sl.ctypes.data_as(_pd),
+                         sw.ctypes.data_as(_pd), shot.fluence, shot.kahn, _d3(*shot.evec))
+        self.xtal = Crystal(
+            C.sizeof(Crystal), _d9(*_arr(shot.cell).ravel()), _d9(*_arr(shot.U).ravel()),
+            um.shape[0], um.ctypes.data_as(_pd), shot.n_phi, shot.phi0, shot.dphi,
+            _d3(*shot.spindle), _d3(*shot.N), int(shot.shape), shot.gauss_c, shot.scale)
+        self.roi_shape = (s1 - s0, f1 - f0)
+
+
+class Fhkl:
+    """Structure factors resident on the current device (xrt_fhkl_create)."""
+
+    def __init__(self, F, hkl_min, F_default=0.0, stream=None):
+        import torch
+        if not (isinstance(F, torch.Tensor) and F.is_cuda and F.dim() == 3):
+            raise TypeError("F must be a 3-D torch tensor on the GPU")
+        if F.dtype not in (torch.float32, torch.float64):
+            raise TypeError("F must be float32 or float64")
+        F = F.contiguous()
+        desc = FhklDesc(C.sizeof(FhklDesc), _i3(*[int(v) for v in hkl_min]), _i3(*F.shape),
+                        XRT_F64 if F.dtype == torch.float64 else XRT_F32, float(F_default))
+        h = C.c_void_p()
+        s = _stream(stream)
+        _check(load().xrt_fhkl_create(C.byref(desc), C.c_void_p(F.data_ptr()), s, C.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_shot(cls, shot, dtype=None, device="cuda"):
+        import torch
+        dtype = torch.float64 if dtype is None else dtype
+        return cls(torch.as_tensor(shot.F, dtype=dtype, device=device), shot.hkl_min, shot.F_default)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _check(load().xrt_fhkl_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+_PREC = {"fp64": XRT_FP64, "mixed": XRT_MIXED}
+
+
+def simulate(shot, fhkl: Fhkl, precision="fp64", out=None, out_dtype=None, accumulate=False,
+             stream=None, roi=None):
+    """Enqueue xrt_simulate for the shot's ROI (or ``roi``) on the stream and
+    return the image tensor (allocated if ``out`` is None)."""
+    import torch
+    st = ShotStructs(shot, roi)
+    if out is None:
+        if out_dtype is None:
+            out_dtype = torch.float64 if precision == "fp64" else torch.float32
+        out = torch.zeros(st.roi_shape, dtype=out_dtype, device="cuda")
+    if tuple(out.shape) != st.roi_shape or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError(f"out must be a contiguous GPU tensor of shape {st.roi_shape}")
+    dt = {torch.float32: XRT_F32, torch.float64: XRT_F64}[out.dtype]
+    _check(load().xrt_simulate(C.byref(st.det), C.byref(st.beam), C.byref(st.xtal), fhkl.handle,
+                               _PREC[precision], C.c_void_p(out.data_ptr()), dt, int(bool(accumulate)),
+                               _stream(stream)))
+    return out
+
+
+def cell_mats(shot) -> np.ndarray:
+    st = ShotStructs(shot)
+    out = np.empty((shot.n_phi * shot.umats.shape[0], 3, 3))
+    _check(load().xrt_cell_mats(C.byref(st.xtal), out.ctypes.data))
+    return out
+
+
+def trace_terms(shot, idx):
+    """S and h of single terms on the device; idx (n, 6) int32."""
+    st = ShotStructs(shot)
+    idx = _arr(idx, np.int32)
+    S = np.empty((len(idx), 3))
+    h = np.empty((len(idx), 3))
+    _check(load().xrt_trace_terms(C.byref(st.det), C.byref(st.beam), C.byref(st.xtal), len(idx),
+                                  idx.ctypes.data, S.ctypes.data, h.ctypes.data))
+    return S, h

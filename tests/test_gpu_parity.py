@@ -1,0 +1,220 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: binary64 path <= 1e-12 relative per pixel (max over pixels with
+a nonzero reference; zero pixels must be zero); mixed path <= 1e-5.  S and h
+must agree bit for bit, which is what keeps ill-conditioned single-term
+pixels inside 1e-12.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as o
+from tests.metrics import compare
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2205_07976_amd import xrt  # noqa: E402
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_image(shot, precision="fp64", roi=None, fhkl=None, **kw):
+    fh = fhkl or xrt.Fhkl.from_shot(shot)
+    out = xrt.simulate(shot, fh, precision=precision, roi=roi, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def random_terms(shot, n, seed):
+    rng = np.random.default_rng(seed)
+    f0, f1, s0, s1 = shot.roi
+    cols = [rng.integers(f0, f1, n), rng.integers(s0, s1, n), rng.integers(0, shot.oversample ** 2, n),
+            rng.integers(0, shot.n_layers, n), rng.integers(0, shot.n_src, n),
+            rng.integers(0, shot.n_phi * shot.n_mos, n)]
+    return np.stack(cols, 1).astype(np.int32)
+
+
+# ------------------------------------------------------------------ S and h -
+@pytest.mark.parametrize("name", ["tiny", "micro", "full"])
+def test_trace_bitwise(name):
+    shot = {"tiny": synth.tiny_shot, "micro": synth.micro_shot, "full": synth.full_shot}[name]()
+    idx = random_terms(shot, 4096, 1)
+    say(f"trace {name}: {len(idx)} terms")
+    S_g, h_g = xrt.trace_terms(shot, idx)
+    S_o, h_o = o.trace(shot, idx)
+    assert np.array_equal(S_g, S_o)
+    assert np.array_equal(h_g, h_o)
+
+
+# ------------------------------------------------------- small full images --
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_tiny_full_image(precision, tol):
+    shot = synth.tiny_shot()
+    say(f"tiny 128x128 {precision}")
+    g = gpu_image(shot, precision)
+    r = compare(g, o.simulate(shot))
+    say(r)
+    assert r["zeros_ok"] and r["max_rel"] <= tol
+
+
+@pytest.mark.parametrize("shape", [synth.SHAPE_SINCG, synth.SHAPE_GAUSS])
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_micro(shape, precision, tol):
+    shot = synth.micro_shot(shape=shape)
+    g = gpu_image(shot, precision)
+    r = compare(g, o.simulate(shot))
+    say("micro", shape, precision, r)
+    assert r["zeros_ok"] and r["max_rel"] <= tol
+
+
+def test_ragged_rois_and_single_pixel():
+    """ROIs that end inside a tile, a single pixel and a single row."""
+    shot = synth.tiny_shot().replace(oversample=3)
+    fh = xrt.Fhkl.from_shot(shot)
+    for roi in [(3, 48, 5, 42), (127, 128, 0, 1), (0, 128, 77, 78), (60, 61, 10, 100)]:
+        g = gpu_image(shot, roi=roi, fhkl=fh)
+        ref = o.simulate(shot.replace(roi=roi))
+        r = compare(g, ref)
+        say(roi, r)
+        assert g.shape == ref.shape and r["zeros_ok"] and r["max_rel"] <= FP64_TOL
+
+
+# ------------------------------------------------- full-size workload -------
+@pytest.fixture(scope="module")
+def full():
+    shot = synth.full_shot()
+    fh = xrt.Fhkl.from_shot(shot)
+    say("full 2463x2527 fp64 launch")
+    img64 = gpu_image(shot, "fp64", fhkl=fh)
+    say("full 2463x2527 mixed launch")
+    img32 = gpu_image(shot, "mixed", fhkl=fh)
+    return shot, fh, img64, img32
+
+
+def test_full_sampled_pixels(full):
+    """The launch the benchmark times, checked at 256 seeded pixels."""
+    shot, _, img64, img32 = full
+    pix = synth.pixel_sample(shot, 256, 2024)
+    ref = o.simulate(shot, pix)
+    g64 = img64[pix[:, 1], pix[:, 0]]
+    g32 = img32[pix[:, 1], pix[:, 0]]
+    r64, r32 = compare(g64, ref), compare(g32, ref)
+    say("full fp64", r64, "mixed", r32)
+    assert r64["zeros_ok"] and r64["max_rel"] <= FP64_TOL
+    assert r32["zeros_ok"] and r32["max_rel"] <= MIXED_TOL
+
+
+@pytest.mark.parametrize("roi", [(1210, 1255, 1245, 1282), (2420, 2463, 0, 29)])
+def test_full_crops(full, roi):
+    """Crops at the beam centre and at a corner (ragged tiles), as separate
+    ROI launches and as windows of the full-size image."""
+    shot, fh, img64, img32 = full
+    ref = o.simulate(shot.replace(roi=roi))
+    f0, f1, s0, s1 = roi
+    win64 = img64[s0:s1, f0:f1]
+    win32 = img32[s0:s1, f0:f1]
+    roi64 = gpu_image(shot, "fp64", roi=roi, fhkl=fh)
+    for name, x, tol in [("win64", win64, FP64_TOL), ("roi64", roi64, FP64_TOL), ("win32", win32, MIXED_TOL)]:
+        r = compare(x, ref)
+        say(roi, name, r)
+        assert r["zeros_ok"] and r["max_rel"] <= tol
+    assert np.array_equal(win64, roi64)
+
+
+def test_full_gauss_sampled():
+    shot = synth.full_shot(shape=synth.SHAPE_GAUSS)
+    roi = (900, 1100, 1500, 1564)
+    g = gpu_image(shot, "fp64", roi=roi)
+    ref = o.simulate(shot.replace(roi=roi))
+    r = compare(g, ref)
+    say("gauss fp64", r)
+    assert r["zeros_ok"] and r["max_rel"] <= FP64_TOL
+    m = gpu_image(shot, "mixed", roi=roi)
+    rm = compare(m, ref)
+    say("gauss mixed", rm)
+    assert rm["floored"] <= MIXED_TOL
+
+
+# ------------------------------------------------------------ invariants ----
+def test_invariants_bitwise():
+    """Friedel (cell -> -cell), fluence doubling and repeat launches leave the
+    GPU image unchanged in every bit, as they do the oracle's."""
+    shot = synth.tiny_shot().replace(oversample=2)
+    fh = xrt.Fhkl.from_shot(shot)
+    for prec in ("fp64", "mixed"):
+        a = gpu_image(shot, prec, fhkl=fh)
+        assert np.array_equal(a, gpu_image(shot, prec, fhkl=fh))
+        assert np.array_equal(a, gpu_image(shot.replace(cell=-shot.cell), prec, fhkl=fh))
+        assert np.array_equal(2 * a, gpu_image(shot.replace(fluence=2 * shot.fluence), prec, fhkl=fh))
+
+
+def test_rotation_about_beam_bitwise():
+    from tests.test_oracle_pins import _rot_shot
+    shot = _rot_shot()
+    U2 = np.stack([-shot.U[1], shot.U[0], shot.U[2]])
+    a = gpu_image(shot)
+    b = gpu_image(shot.replace(U=U2))
+    n = 16
+    moved = np.empty_like(a)
+    for i_s in range(n):
+        for i_f in range(n):
+            moved[i_f, n - 1 - i_s] = a[i_s, i_f]
+    assert np.array_equal(moved, b)
+
+
+def test_accumulate_and_output_types():
+    """accumulate adds into the image (the fused add-image step) and the
+    binary32 output is the rounded binary64 value."""
+    shot = synth.tiny_shot()
+    fh = xrt.Fhkl.from_shot(shot)
+    base = torch.full((128, 128), 0.25, dtype=torch.float64, device="cuda")
+    xrt.simulate(shot, fh, out=base, accumulate=True)
+    once = gpu_image(shot, fhkl=fh)
+    torch.cuda.synchronize()
+    assert np.array_equal(base.cpu().numpy(), once + 0.25)
+    f32 = gpu_image(shot, out_dtype=torch.float32, fhkl=fh)
+    assert np.array_equal(f32, once.astype(np.float32).astype(np.float64))
+
+
+def test_fhkl_f32_source_and_default():
+    """A binary32 table and a table no reflection reaches (default only)."""
+    shot = synth.micro_shot()
+    fh32 = xrt.Fhkl.from_shot(shot, dtype=torch.float32)
+    g = gpu_image(shot, fhkl=fh32)
+    ref = o.simulate(shot.replace(F=shot.F.astype(np.float32).astype(np.float64)))
+    assert compare(g, ref)["max_rel"] <= FP64_TOL
+    far = shot.replace(hkl_min=np.array([100, 100, 100]))
+    assert compare(gpu_image(far), o.simulate(far))["max_rel"] <= FP64_TOL
+
+
+def test_extreme_N_and_unit_crystal():
+    for N in ([1.0, 1.0, 1.0], [1000.0, 1.0, 37.0]):
+        shot = synth.micro_shot().replace(N=np.array(N))
+        r = compare(gpu_image(shot), o.simulate(shot))
+        say(N, r)
+        assert r["max_rel"] <= FP64_TOL
+
+
+def test_exact_bragg_on_gpu():
+    from tests import geometry as geo
+    base = synth.tiny_shot().replace(N=np.array([5.0, 6.0, 7.0]))
+    lam, U = geo.bragg_orientation(base, 90, 40, (2, -1, 3))
+    shot = base.replace(U=U, src_lambda=np.array([lam]))
+    g = gpu_image(shot, roi=(90, 91, 40, 41))[0, 0]
+    x, y, z = geo.pixel_xyz(shot, 90, 40)
+    F = shot.F[22, 19, 23]
+    expect = (geo.R_E ** 2 * shot.fluence * F * F * (5 * 6 * 7) ** 2 * geo.kahn_xy(0.0, x, y, z)
+              * geo.flat_solid_angle(shot.pixel, x, y, z))
+    assert abs(g - expect) / expect <= FP64_TOL
+    m = gpu_image(shot, "mixed", roi=(90, 91, 40, 41))[0, 0]
+    assert abs(m - expect) / expect <= MIXED_TOL
