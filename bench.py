@@ -19,12 +19,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Lane-issue slots of the binary64 / mixed inner term (sincg), counted from
-# the operation list of the spots kernel: fixed before tuning.  A slot is one
-# wave64 lane-op at full rate; transcendentals (rcp) count 4.
-C_ALG = {"fp64": 115, "mixed": 98}
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz
-PEAK_SLOTS = 256 * 64 * 2.4e9
+# Algorithmic VALU work of one pixel term (sincg inner loop), in FP32-lane-op
+# equivalents: a binary32 or 32-bit integer op counts 1, a binary64 op or a
+# conversion from binary64 counts 2 (binary64 runs at half the binary32 rate),
+# a binary32 transcendental counts 4 (quarter rate), a binary64 reciprocal 8.
+#   binary64: h = M S 12 ops; per axis 24 ops (rint, sub, max, N*f, rint, sub,
+#             two squares, 2 x 7 FMA Horner, two products); 4 products;
+#             reciprocal, one Newton step and a residual correction (rcp + 5);
+#             square and FMA accumulate 2; table offset 3 FMA
+#             -> 24 + 144 + 8 + 18 + 4 + 6 = 204
+#   mixed:    h 12 binary64 ops; per axis 6 binary64 ops, 2 conversions and 12
+#             binary32 ops; 4 products; rcp + mul; square and F^2 product;
+#             Kahan 4; table offset 3 binary64 FMA
+#             -> 24 + 84 + 4 + 5 + 2 + 4 + 6 = 129
+C_ALG = {"fp64": 204, "mixed": 129}
+# MI355X binary32 VALU peak: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz
+# = 78.64 T lane-op/s (157.3 TFLOP/s counting an FMA as 2 flops)
+PEAK_OPS = 256 * 4 * 32 * 2.4e9
+# HBM bytes per binary64 launch from the FETCH_SIZE / WRITE_SIZE counters
+# (scaled by a 1 GiB copy), or None when the kernel changed since.
+TRAFFIC_FP64 = None
 
 
 def log(*a):
@@ -88,6 +102,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="finish with one device-to-device copy of this many MiB (a kernel of known "
+                         "traffic that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); shots would be sharded "
@@ -117,13 +134,13 @@ def main():
         "config": {"workload": "full-size shot, binary64: 2463x2527 px, oversample 2, 3 layers, "
                                "100 sources, 50 mosaic domains, sincg N=20, Fhkl [-60,60]^3",
                    "pixels": shot.n_pixels, "terms_per_pixel": shot.terms_per_pixel, "terms": terms},
-        "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_SLOTS / 1e12,
-                     "unit": "Tlane-op/s", "frac": ach / PEAK_SLOTS, "traffic": None,
+        "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_OPS / 1e12,
+                     "unit": "T fp32-lane-op/s", "frac": ach / PEAK_OPS, "traffic": TRAFFIC_FP64,
                      "kernel": "spots_kernel<FP64,SINCG>", "kernel_ms": kern_ms,
-                     "c_alg_slots_per_term": C_ALG["fp64"]},
+                     "c_alg_per_term": C_ALG["fp64"]},
     }
     log(f"fp64: {ms:.1f} ms/step (events {kern_ms:.1f} ms), {value:.1f} Gterm/s, "
-        f"roofline frac {ach / PEAK_SLOTS:.3f}")
+        f"roofline frac {ach / PEAK_OPS:.3f}")
 
     if not args.no_mixed:
         img32, wall32, ev32 = time_form(shot, fh, "mixed", args.steps, args.warmup)
@@ -132,9 +149,18 @@ def main():
         a32 = C_ALG["mixed"] * terms / (k32 * 1e-3)
         emax, erms = mixed_error(shot, img32.cpu().numpy())
         res["mixed"] = {"value": v32, "unit": "Gterm/s", "ms_per_step": 1e3 * wall32 / args.steps,
-                        "kernel_ms": k32, "frac": a32 / PEAK_SLOTS, "speedup_vs_fp64": v32 / value,
+                        "kernel_ms": k32, "frac": a32 / PEAK_OPS, "speedup_vs_fp64": v32 / value,
                         "max_rel_err": emax, "rms_rel_err": erms, "err_sample": "256 seeded pixels"}
         log(f"mixed: {1e3 * wall32 / args.steps:.1f} ms/step, {v32:.1f} Gterm/s, max rel err {emax:.2e}")
+
+    if args.copy_mib:
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_mib} MiB read + {args.copy_mib} MiB written")
 
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(shot)

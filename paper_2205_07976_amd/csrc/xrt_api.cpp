@@ -239,11 +239,64 @@ void fill_params(const xrt_detector *d, const xrt_beam *b, const xrt_crystal *x,
 
 struct xrt_fhkl {
     int device;
-    int32_t lo[3], hi[3];
-    int32_t sa, sb;
+    int32_t lo[3], hi[3];  // padded box of integer h (hkl_min - PAD .. hkl_max + PAD)
+    int32_t sa, sb;        // element strides of the h and k axes in the padded box
     double *F2_64;
     float *F2_32;
+    uint32_t bytes64, bytes32;
 };
+
+namespace {
+
+// 2^52 plus the byte offset of h = (0, 0, 0) relative to the table start
+// (an exact binary64 integer; see table_offset in the kernels).
+double biased_zero_offset(const xrt_fhkl *t, int64_t esize)
+{
+    const int64_t o = -((int64_t)t->lo[0] * t->sa + (int64_t)t->lo[1] * t->sb + t->lo[2]) * esize;
+    return 4503599627370496.0 + (double)o;
+}
+
+// True when every rint(h) of the shot provably lies in the padded box, so the
+// kernels may skip the clamp.  |h_i| = |a'_i . S| <= |a'_i| max|S|, and
+// |S| = |d - dir_j| / lambda_j = 2 sin(angle(d, dir_j)/2) / lambda_j.  The
+// sample points fill a box (detector rectangle x layer depths); if every
+// vertex is within 90 degrees of dir_j, the cone of directions within the
+// largest vertex angle is convex and holds the whole box, so the vertices
+// bound the angle; otherwise |d - dir_j| <= 2.
+bool h_inside(const xrt_detector *d, const xrt_beam *b, const double *mats, size_t n_rot,
+              const xrt_fhkl *t)
+{
+    double Fr[2] = {d->roi_f0 * d->pixel - d->beam_f, d->roi_f1 * d->pixel - d->beam_f};
+    double Sr[2] = {d->roi_s0 * d->pixel - d->beam_s, d->roi_s1 * d->pixel - d->beam_s};
+    double Lr[2] = {d->distance, d->distance + (double)(d->n_layers - 1) * d->layer_dt};
+    double smax = 0.0;
+    for (int j = 0; j < b->n_src; ++j) {
+        const double *inc = b->dir + 3 * j;
+        double cmin = 1.0;
+        for (int a = 0; a < 8; ++a) {
+            double r[3];
+            for (int i = 0; i < 3; ++i)
+                r[i] = Fr[a & 1] * d->fdet[i] + Sr[(a >> 1) & 1] * d->sdet[i] + Lr[a >> 2] * d->odet[i];
+            const double n = std::sqrt(dot3(r, r));
+            cmin = std::fmin(cmin, dot3(r, inc) / n);
+        }
+        const double chord = cmin > 1e-6 ? std::sqrt(2.0 - 2.0 * cmin) : 2.0;
+        smax = std::fmax(smax, chord / b->lambda[j]);
+    }
+    smax = smax * (1.0 + 1e-9) + 1e-12;
+    for (int i = 0; i < 3; ++i) {
+        double rmax = 0.0;
+        for (size_t r = 0; r < n_rot; ++r) {
+            const double *row = mats + 9 * r + 3 * i;
+            rmax = std::fmax(rmax, std::sqrt(dot3(row, row)));
+        }
+        const double bound = std::ceil(rmax * smax * (1.0 + 1e-9) + 1e-9) + 1.0;
+        if (!(bound < 1e9) || -bound < t->lo[i] || bound > t->hi[i]) return false;
+    }
+    return true;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -266,18 +319,17 @@ xrt_status xrt_fhkl_create(const xrt_fhkl_desc *desc, const void *dev_F, void *s
                     sizeof(xrt_fhkl_desc));
     if (desc->dtype != XRT_F32 && desc->dtype != XRT_F64) return fail(XRT_EINVAL, "dtype must be XRT_F32 or XRT_F64");
     if (!is_fin(desc->F_default)) return fail(XRT_EINVAL, "F_default must be finite");
-    int64_t padded = 1;
+    const int P = xrt::FHKL_PAD;
+    int64_t n[3], padded = 1;
     for (int i = 0; i < 3; ++i) {
         if (desc->hkl_count[i] < 1) return fail(XRT_EINVAL, "hkl_count[%d] must be >= 1", i);
         if (desc->hkl_min[i] < -(1 << 20) || desc->hkl_min[i] > (1 << 20) ||
             (int64_t)desc->hkl_min[i] + desc->hkl_count[i] > (1 << 20))
             return fail(XRT_ERANGE, "axis %d: table must lie within |h| <= 2^20", i);
-        padded *= (int64_t)desc->hkl_count[i] + 2;
+        n[i] = (int64_t)desc->hkl_count[i] + 2 * P;
+        padded *= n[i];
     }
     if (padded >= (int64_t)1 << 28) return fail(XRT_ERANGE, "padded table has 2^28 or more entries");
-    const int64_t sb = (int64_t)desc->hkl_count[2] + 2;
-    const int64_t sa = ((int64_t)desc->hkl_count[1] + 2) * sb;
-    if (sa >= (1 << 24)) return fail(XRT_ERANGE, "(nk+2)*(nl+2) must be below 2^24");
 
     xrt_fhkl *t = new (std::nothrow) xrt_fhkl();
     if (!t) return fail(XRT_ENOMEM, "host allocation failed");
@@ -287,7 +339,7 @@ xrt_status xrt_fhkl_create(const xrt_fhkl_desc *desc, const void *dev_F, void *s
     hipStream_t s = (hipStream_t)stream;
     if (e == hipSuccess)
         e = xrt::launch_pad_table(dev_F, desc->dtype == XRT_F64, desc->hkl_count[0], desc->hkl_count[1],
-                                  desc->hkl_count[2], desc->F_default, t->F2_64, t->F2_32, s);
+                                  desc->hkl_count[2], P, desc->F_default, t->F2_64, t->F2_32, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipFree(t->F2_64);
@@ -296,11 +348,13 @@ xrt_status xrt_fhkl_create(const xrt_fhkl_desc *desc, const void *dev_F, void *s
         return hip_fail(e, "xrt_fhkl_create");
     }
     for (int i = 0; i < 3; ++i) {
-        t->lo[i] = desc->hkl_min[i] - 1;
-        t->hi[i] = desc->hkl_min[i] + desc->hkl_count[i];
+        t->lo[i] = desc->hkl_min[i] - P;
+        t->hi[i] = desc->hkl_min[i] + desc->hkl_count[i] - 1 + P;
     }
-    t->sa = (int32_t)sa;
-    t->sb = (int32_t)sb;
+    t->sb = (int32_t)n[2];
+    t->sa = (int32_t)(n[1] * n[2]);
+    t->bytes64 = (uint32_t)(sizeof(double) * padded);
+    t->bytes32 = (uint32_t)(sizeof(float) * padded);
     *out = t;
     return XRT_OK;
 }
@@ -351,12 +405,19 @@ xrt_status xrt_simulate(const xrt_detector *det, const xrt_beam *beam, const xrt
     fill_params(det, beam, xtal, p);
     p.F2_64 = fhkl->F2_64;
     p.F2_32 = fhkl->F2_32;
+    p.bytes64 = fhkl->bytes64;
+    p.bytes32 = fhkl->bytes32;
     for (int i = 0; i < 3; ++i) {
-        p.lo[i] = fhkl->lo[i];
-        p.hi[i] = fhkl->hi[i];
+        p.lo_d[i] = fhkl->lo[i];
+        p.hi_d[i] = fhkl->hi[i];
     }
-    p.sa = fhkl->sa;
-    p.sb = fhkl->sb;
+    p.sa8 = 8.0 * fhkl->sa;
+    p.sb8 = 8.0 * fhkl->sb;
+    p.sa4 = 4.0 * fhkl->sa;
+    p.sb4 = 4.0 * fhkl->sb;
+    p.off8 = biased_zero_offset(fhkl, 8);
+    p.off4 = biased_zero_offset(fhkl, 4);
+    const bool clamp = !h_inside(det, beam, host.data(), n_rot, fhkl);
     p.image = dev_image;
     p.out_f64 = out_dtype == XRT_F64;
     p.accumulate = accumulate;
@@ -368,7 +429,7 @@ xrt_status xrt_simulate(const xrt_detector *det, const xrt_beam *beam, const xrt
     if (e == hipSuccess) {
         p.mats = tables;
         p.src = tables + 9 * n_rot;
-        e = xrt::launch_spots(p, precision, s);
+        e = xrt::launch_spots(p, precision, clamp, s);
     }
     hipError_t e2 = hipFreeAsync(tables, s);
     if (e != hipSuccess) return hip_fail(e, "xrt_simulate");

@@ -22,6 +22,11 @@ enum { SRC_DIR = 0, SRC_LAMBDA = 3, SRC_WEIGHT = 4, SRC_E = 5, SRC_B = 8 };
 // removes the 0/0 at f = 0 without a branch or select.
 constexpr double F_FLOOR = 2.3283064365386963e-10;  // 2^-32
 
+// Layers of F_default around a structure-factor table.  When the host can
+// prove that every rint(h) of a shot lies inside the padded box, the kernels
+// index the table without clamping.
+constexpr int FHKL_PAD = 8;
+
 struct Params {
     // detector and sample-point geometry (binary64)
     double pixel, distance, beam_f, beam_s;
@@ -39,12 +44,16 @@ struct Params {
     double ln_n2;          // Gaussian: log(prod N_i^2)
     double kahn;
     double norm;           // r_e^2 fluence scale / (O^2 n_phi n_mos)
-    // structure factors: padded tables of F^2, with one layer of F_default
-    // around the tabulated box
+    // structure factors: tables of F^2 with FHKL_PAD layers of F_default^2
+    // around the tabulated box.  The byte offset of entry h0 in the binary64
+    // (binary32) table is h0_a*sa8 + h0_b*sb8 + h0_c*8 + off8 - 2^52, exact in
+    // binary64 (sa4, ..., off4 likewise), for h0 in [lo_d, hi_d].
     const double *F2_64;
     const float *F2_32;
-    int32_t lo[3], hi[3];  // clamp range of h0 (hkl_min - 1, hkl_max + 1)
-    int32_t sa, sb;        // padded strides of the h and k axes
+    uint32_t bytes64, bytes32;
+    double lo_d[3], hi_d[3];
+    double sa8, sb8, sa4, sb4;
+    double off8, off4;
     // per-shot tables in device memory
     const double *mats;    // [n_rot][9]
     const double *src;     // [n_src][SRC_STRIDE]
@@ -55,9 +64,10 @@ struct Params {
 };
 
 // Launchers (xrt_kernels.hip).  Return the hipError_t of the launch.
-hipError_t launch_spots(const Params &p, int precision, hipStream_t stream);
+hipError_t launch_spots(const Params &p, int precision, bool clamp, hipStream_t stream);
 hipError_t launch_pad_table(const void *src, int src_f64, int32_t na, int32_t nb, int32_t nc,
-                            double F_default, double *F2_64, float *F2_32, hipStream_t stream);
+                            int32_t pad, double F_default, double *F2_64, float *F2_32,
+                            hipStream_t stream);
 hipError_t launch_trace(const Params &p, int64_t n, const int32_t *idx, double *S, double *h,
                         hipStream_t stream);
 

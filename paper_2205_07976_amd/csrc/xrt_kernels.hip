@@ -89,26 +89,64 @@ __device__ __forceinline__ void miller(const double *M, const double S[3], doubl
         h[i] = __builtin_fma(M[3 * i + 2], S[2], M[3 * i] * S[0] + M[3 * i + 1] * S[1]);
 }
 
-// Index of the nearest reflection in the padded F^2 table.  Entries outside
-// the tabulated box clamp onto the border layer, which holds F_default^2.
-__device__ __forceinline__ int table_index(const Params &p, const double hr[3])
+// Byte offset of the nearest reflection h0 in a padded F^2 table, from the
+// rounded indices hr (exact small integers in binary64):
+//   x = 2^52 + off + hr_a*sa + hr_b*sb + hr_c*esize
+// by three FMAs.  Every partial sum is an integer below 2^53, so x is exact,
+// and for 0 <= offset < 2^32 the low 32 bits of x are the offset itself (the
+// 2^52 bias fixes the exponent), which saves the float-to-int conversions.
+// CLAMP moves indices outside the padded box onto its border layer
+// (F_default^2); without it the host has proven every h0 of the shot inside.
+template <bool CLAMP>
+__device__ __forceinline__ uint32_t table_offset(const Params &p, const double hr[3], double sa,
+                                                 double sb, double sc, double off)
 {
-    int q[3];
+    double v[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        int v = (int)hr[i];  // v_cvt_i32_f64 saturates
-        v = v < p.lo[i] ? p.lo[i] : v;
-        v = v > p.hi[i] ? p.hi[i] : v;
-        q[i] = v - p.lo[i];
-    }
-    return __umul24(q[0], p.sa) + __umul24(q[1], p.sb) + q[2];
+    for (int i = 0; i < 3; ++i)
+        v[i] = CLAMP ? __builtin_fmin(__builtin_fmax(hr[i], p.lo_d[i]), p.hi_d[i]) : hr[i];
+    double x = __builtin_fma(v[2], sc, off);
+    x = __builtin_fma(v[1], sb, x);
+    x = __builtin_fma(v[0], sa, x);
+    return (uint32_t)__builtin_bit_cast(uint64_t, x);
+}
+
+// Gathers through a buffer resource: a 32-bit offset per lane, no 64-bit
+// address arithmetic, and the hardware range check returns 0 (never a fault)
+// for an offset past the table.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t table_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ double load_f64(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
+__device__ __forceinline__ float load_f32(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+
+// n / d for the lattice ratio: the hardware reciprocal (relative error below
+// 2^-24 on gfx950), one Newton step (error squared, ~2^-48) and a residual
+// correction of the quotient, which lands within an ulp or two for the normal
+// operands met here.  The lattice factor is not part of the bit-exact S/h
+// sequence.
+__device__ __forceinline__ double div_newton(double n, double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
+    const double q = n * r;
+    return __builtin_fma(r, __builtin_fma(-d, q, n), q);
 }
 
 // ---------------------------------------------------------------------------
 // One term F^2 L^2, binary64.
 // ---------------------------------------------------------------------------
-template <int SHAPE>
-__device__ __forceinline__ double term_f64(const Params &p, const double h[3])
+template <int SHAPE, bool CLAMP>
+__device__ __forceinline__ double term_f64(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3])
 {
     double hr[3];
     double L2;
@@ -123,7 +161,7 @@ __device__ __forceinline__ double term_f64(const Params &p, const double h[3])
             num *= g * sinpi_over_x(g * g);
             den *= fa * sinpi_over_x(fa * fa);
         }
-        const double q = num / den;
+        const double q = div_newton(num, den);
         L2 = q * q;
     } else {
         double e = p.ln_n2;
@@ -135,13 +173,13 @@ __device__ __forceinline__ double term_f64(const Params &p, const double h[3])
         }
         L2 = exp(e);
     }
-    return p.F2_64[table_index(p, hr)] * L2;
+    return load_f64(tab, table_offset<CLAMP>(p, hr, p.sa8, p.sb8, 8.0, p.off8)) * L2;
 }
 
 // One term, mixed: h, f and g in binary64 (they decide the conditioning),
 // everything after the reduced arguments in binary32.
-template <int SHAPE>
-__device__ __forceinline__ float term_mixed(const Params &p, const double h[3])
+template <int SHAPE, bool CLAMP>
+__device__ __forceinline__ float term_mixed(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3])
 {
     double hr[3];
     float L2;
@@ -169,7 +207,7 @@ __device__ __forceinline__ float term_mixed(const Params &p, const double h[3])
         }
         L2 = __expf((float)(e + p.ln_n2));
     }
-    return p.F2_32[table_index(p, hr)] * L2;
+    return load_f32(tab, table_offset<CLAMP>(p, hr, p.sa4, p.sb4, 4.0, p.off4)) * L2;
 }
 
 __device__ __forceinline__ void kahn_add(float &s, float &c, float x)
@@ -189,9 +227,11 @@ __device__ __forceinline__ int xcd_tile(int bid, int n_tiles)
     return x * q + (x < r ? x : r) + k;
 }
 
-template <int PREC, int SHAPE>
+template <int PREC, int SHAPE, bool CLAMP>
 __global__ __launch_bounds__(BLOCK) void spots_kernel(const Params p)
 {
+    const __amdgpu_buffer_rsrc_t tab = PREC == XRT_FP64 ? table_rsrc(p.F2_64, p.bytes64)
+                                                         : table_rsrc(p.F2_32, p.bytes32);
     const int tile = xcd_tile(blockIdx.x, p.n_tiles);
     const int tf = tile % p.tiles_f, ts = tile / p.tiles_f;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -220,7 +260,7 @@ __global__ __launch_bounds__(BLOCK) void spots_kernel(const Params p)
                         for (int r = 0; r < p.n_rot; ++r) {
                             double h[3];
                             miller(p.mats + 9 * r, S, h);
-                            sub += term_f64<SHAPE>(p, h);
+                            sub += term_f64<SHAPE, CLAMP>(p, tab, h);
                         }
                         acc64 = __builtin_fma(w, sub, acc64);
                     } else {
@@ -228,7 +268,7 @@ __global__ __launch_bounds__(BLOCK) void spots_kernel(const Params p)
                         for (int r = 0; r < p.n_rot; ++r) {
                             double h[3];
                             miller(p.mats + 9 * r, S, h);
-                            kahn_add(s, c, term_mixed<SHAPE>(p, h));
+                            kahn_add(s, c, term_mixed<SHAPE, CLAMP>(p, tab, h));
                         }
                         kahn_add(acc, accc, (float)w * (s - c));
                     }
@@ -246,40 +286,49 @@ __global__ __launch_bounds__(BLOCK) void spots_kernel(const Params p)
     }
 }
 
-hipError_t launch_spots(const Params &p, int precision, hipStream_t stream)
+template <int PREC, int SHAPE>
+static void launch_one(const Params &p, bool clamp, hipStream_t stream)
 {
     dim3 grid(p.n_tiles), block(BLOCK);
+    if (clamp)
+        hipLaunchKernelGGL((spots_kernel<PREC, SHAPE, true>), grid, block, 0, stream, p);
+    else
+        hipLaunchKernelGGL((spots_kernel<PREC, SHAPE, false>), grid, block, 0, stream, p);
+}
+
+hipError_t launch_spots(const Params &p, int precision, bool clamp, hipStream_t stream)
+{
     if (precision == XRT_FP64) {
         if (p.shape == XRT_SHAPE_SINCG)
-            hipLaunchKernelGGL((spots_kernel<XRT_FP64, XRT_SHAPE_SINCG>), grid, block, 0, stream, p);
+            launch_one<XRT_FP64, XRT_SHAPE_SINCG>(p, clamp, stream);
         else
-            hipLaunchKernelGGL((spots_kernel<XRT_FP64, XRT_SHAPE_GAUSS>), grid, block, 0, stream, p);
+            launch_one<XRT_FP64, XRT_SHAPE_GAUSS>(p, clamp, stream);
     } else {
         if (p.shape == XRT_SHAPE_SINCG)
-            hipLaunchKernelGGL((spots_kernel<XRT_MIXED, XRT_SHAPE_SINCG>), grid, block, 0, stream, p);
+            launch_one<XRT_MIXED, XRT_SHAPE_SINCG>(p, clamp, stream);
         else
-            hipLaunchKernelGGL((spots_kernel<XRT_MIXED, XRT_SHAPE_GAUSS>), grid, block, 0, stream, p);
+            launch_one<XRT_MIXED, XRT_SHAPE_GAUSS>(p, clamp, stream);
     }
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Padded F^2 tables: entry (a, b, c) of the (na+2)(nb+2)(nc+2) box holds
-// F(a-1, b-1, c-1)^2 inside and F_default^2 on the border layer.
+// Padded F^2 tables: entry (a, b, c) of the (na+2P)(nb+2P)(nc+2P) box holds
+// F(a-P, b-P, c-P)^2 inside the tabulated range and F_default^2 elsewhere.
 // ---------------------------------------------------------------------------
-__global__ void pad_table_kernel(const void *src, int src_f64, int na, int nb, int nc,
+__global__ void pad_table_kernel(const void *src, int src_f64, int na, int nb, int nc, int pad,
                                  double F_default, double *F2_64, float *F2_32)
 {
-    const int pb = nb + 2, pc = nc + 2;
-    const int64_t total = (int64_t)(na + 2) * pb * pc;
+    const int pb = nb + 2 * pad, pc = nc + 2 * pad;
+    const int64_t total = (int64_t)(na + 2 * pad) * pb * pc;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % pc);
-        const int b = (int)((i / pc) % pb);
-        const int a = (int)(i / ((int64_t)pb * pc));
+        const int c = (int)(i % pc) - pad;
+        const int b = (int)((i / pc) % pb) - pad;
+        const int a = (int)(i / ((int64_t)pb * pc)) - pad;
         double F = F_default;
-        if (a >= 1 && a <= na && b >= 1 && b <= nb && c >= 1 && c <= nc) {
-            const int64_t s = ((int64_t)(a - 1) * nb + (b - 1)) * nc + (c - 1);
+        if (a >= 0 && a < na && b >= 0 && b < nb && c >= 0 && c < nc) {
+            const int64_t s = ((int64_t)a * nb + b) * nc + c;
             F = src_f64 ? ((const double *)src)[s] : (double)((const float *)src)[s];
         }
         F2_64[i] = F * F;
@@ -288,10 +337,11 @@ __global__ void pad_table_kernel(const void *src, int src_f64, int na, int nb, i
 }
 
 hipError_t launch_pad_table(const void *src, int src_f64, int32_t na, int32_t nb, int32_t nc,
-                            double F_default, double *F2_64, float *F2_32, hipStream_t stream)
+                            int32_t pad, double F_default, double *F2_64, float *F2_32,
+                            hipStream_t stream)
 {
     hipLaunchKernelGGL(pad_table_kernel, dim3(1024), dim3(256), 0, stream, src, src_f64, na, nb,
-                       nc, F_default, F2_64, F2_32);
+                       nc, pad, F_default, F2_64, F2_32);
     return hipGetLastError();
 }
 

@@ -218,3 +218,16 @@ def test_exact_bragg_on_gpu():
     assert abs(g - expect) / expect <= FP64_TOL
     m = gpu_image(shot, "mixed", roi=(90, 91, 40, 41))[0, 0]
     assert abs(m - expect) / expect <= MIXED_TOL
+
+
+def test_clamped_index_path():
+    """A cell so large that h leaves the padded table box: the kernels take
+    the clamping index path (out-of-box reflections read F_default)."""
+    base = synth.micro_shot()
+    shot = base.replace(cell=8.0 * base.cell)
+    S, h = o.trace(shot, random_terms(shot, 256, 3))
+    assert np.abs(np.rint(h)).max() > 12  # beyond hkl range 4 + padding 8
+    for prec, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
+        r = compare(gpu_image(shot, prec), o.simulate(shot))
+        say("clamp", prec, r)
+        assert r["zeros_ok"] and r["max_rel"] <= tol
