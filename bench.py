@@ -36,9 +36,10 @@ C_ALG = {"fp64": 204, "mixed": 129}
 # MI355X binary32 VALU peak: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz
 # = 78.64 T lane-op/s (157.3 TFLOP/s counting an FMA as 2 flops)
 PEAK_OPS = 256 * 4 * 32 * 2.4e9
-# HBM bytes per binary64 launch from the FETCH_SIZE / WRITE_SIZE counters
-# (scaled by a 1 GiB copy), or None when the kernel changed since.
-TRAFFIC_FP64 = None
+# HBM bytes per binary64 launch from the FETCH_SIZE / WRITE_SIZE counters,
+# each scaled by what it reads for a 1 GiB device copy (profiles/
+# spots_full_shot_counters.txt); set to None whenever the kernel changes.
+TRAFFIC_FP64 = 50.13e6
 
 
 def log(*a):
