@@ -96,6 +96,61 @@ def mixed_error(shot, img32):
     return float(r.max()), float(np.sqrt(np.mean(r * r)))
 
 
+def adjoint_bench(steps):
+    """The refinement workload: 512 regions of 32 x 32 pixels around predicted
+    spots of the full-size crystal with the Gaussian shape (60000 terms per
+    pixel); squared-residual loss against a target simulated at perturbed
+    parameters with Poisson noise; forward (regions) + adjoint per step."""
+    import math
+    import numpy as np
+    import torch
+    import synth
+    from paper_2205_07976_amd import refine, xrt
+    shot, origins = synth.roi_shot()
+    fh = xrt.Fhkl.from_shot(shot)
+    size = (32, 32)
+    abc_t, beta_t, N_t, th_t, s_t = refine.perturbed(np.array([79.0, 79.0, 38.0]), math.radians(95.0),
+                                                     shot.N, 1.0)
+    Mt = refine.m0_from_params(torch.tensor(abc_t), torch.tensor(beta_t), torch.tensor(th_t), shot.U).numpy()
+    clean = xrt.simulate_rois(shot.replace(U=np.eye(3), cell=Mt, N=N_t, scale=s_t), fh, origins, size)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    k = 1e4 / float(clean.max())
+    target = torch.poisson(clean * k, generator=gen) / k
+    base = shot.replace(U=np.eye(3), cell=(shot.U @ shot.cell.T).T.copy())
+    terms = len(origins) * size[0] * size[1] * shot.terms_per_pixel
+    out = {"workload": "512 ROIs of 32x32 px around predicted spots, Gaussian N=20, 60000 terms/px",
+           "terms_per_pass": terms}
+    grads = {}
+    for prec in ("fp64", "mixed"):
+        img = xrt.simulate_rois(base, fh, origins, size, precision=prec, out_dtype=torch.float64)
+        g = xrt.backward_rois(base, fh, origins, size, 2 * (img - target), precision=prec)
+        torch.cuda.synchronize()
+        ef = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        eb = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for (a, b), (c, d) in zip(ef, eb):
+            a.record()
+            xrt.simulate_rois(base, fh, origins, size, precision=prec, out=img)
+            b.record()
+            r = 2 * (img - target)
+            c.record()
+            xrt.backward_rois(base, fh, origins, size, r, precision=prec, grad=g)
+            d.record()
+        torch.cuda.synchronize()
+        fms = sum(a.elapsed_time(b) for a, b in ef) / steps
+        bms = sum(c.elapsed_time(d) for c, d in eb) / steps
+        grads[prec] = g.cpu().numpy()
+        out[prec] = {"fwd_ms": fms, "bwd_ms": bms, "fwd_Gterm_s": terms / fms / 1e6,
+                     "bwd_Gterm_s": terms / bms / 1e6,
+                     "loss": float(((img - target) ** 2).sum())}
+        log(f"adjoint {prec}: forward {fms:.1f} ms, backward {bms:.1f} ms")
+    d = np.abs(grads["mixed"] - grads["fp64"])
+    out["grad_fp64"] = grads["fp64"].tolist()
+    out["mixed_vs_fp64_max_diff_over_max"] = [float(d[sl].max() / np.abs(grads["fp64"][sl]).max())
+                                              for sl in (slice(0, 9), slice(9, 12), slice(12, 13))]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +158,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the regions-of-interest adjoint")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="finish with one device-to-device copy of this many MiB (a kernel of known "
                          "traffic that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -153,6 +209,9 @@ def main():
                         "kernel_ms": k32, "frac": a32 / PEAK_OPS, "speedup_vs_fp64": v32 / value,
                         "max_rel_err": emax, "rms_rel_err": erms, "err_sample": "256 seeded pixels"}
         log(f"mixed: {1e3 * wall32 / args.steps:.1f} ms/step, {v32:.1f} Gterm/s, max rel err {emax:.2e}")
+
+    if not args.no_adjoint:
+        res["adjoint"] = adjoint_bench(args.steps)
 
     if args.copy_mib:
         n = args.copy_mib * (1 << 20) // 4

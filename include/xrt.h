@@ -175,6 +175,42 @@ xrt_status xrt_simulate(const xrt_detector *det, const xrt_beam *beam,
                         int32_t precision, void *dev_image, int32_t out_dtype,
                         int32_t accumulate, void *stream);
 
+/* Simulate n_roi regions of interest of one shot, all roi_nf x roi_ns pixels,
+ * in one launch (the per-crystal refinement of section II works on the
+ * pixels around predicted Bragg spots).
+ *  host_origins  [n_roi][2] int32 (i_f, i_s) of each region's first pixel;
+ *                every region must lie inside the detector (det's own ROI
+ *                fields are ignored).  Read during the call.
+ *  dev_images    device pointer, [n_roi][roi_ns][roi_nf] of out_dtype,
+ *                overwritten.
+ * Errors: as xrt_simulate; ERANGE for n_roi outside [1, 2^22]. */
+xrt_status xrt_simulate_rois(const xrt_detector *det, const xrt_beam *beam,
+                             const xrt_crystal *xtal, const xrt_fhkl *fhkl,
+                             int32_t precision, int64_t n_roi,
+                             const int32_t *host_origins, int32_t roi_nf,
+                             int32_t roi_ns, void *dev_images, int32_t out_dtype,
+                             void *stream);
+
+/* Adjoint of xrt_simulate_rois for the Gaussian shape (refinement of the
+ * per-crystal parameters against measured images, section II).  Given
+ * dev_dLdI = dL/dI for every pixel of the regions ([n_roi][roi_ns][roi_nf]
+ * of dLdI_dtype, device), writes 13 binary64 values to dev_grad13 (device):
+ *   [0..8]   dL/dM0, M0 = the 3 x 3 matrix whose rows are U a, U b, U c
+ *            (row-major), the cell in the lab frame before spindle and
+ *            mosaic rotations;
+ *   [9..11]  dL/dNa, dL/dNb, dL/dNc;
+ *   [12]     dL/dscale.
+ * The sums are reduced in a fixed order (repeat calls give identical bits).
+ * Scratch memory for the per-workgroup partial sums is taken stream-ordered.
+ * Errors: EINVAL for the sincg shape or scale == 0, otherwise as
+ * xrt_simulate_rois. */
+xrt_status xrt_backward_rois(const xrt_detector *det, const xrt_beam *beam,
+                             const xrt_crystal *xtal, const xrt_fhkl *fhkl,
+                             int32_t precision, int64_t n_roi,
+                             const int32_t *host_origins, int32_t roi_nf,
+                             int32_t roi_ns, const void *dev_dLdI,
+                             int32_t dLdI_dtype, double *dev_grad13, void *stream);
+
 /* Diagnostics: the library's lab-frame cell matrices M_{k,m} (host output,
  * [n_phi*n_mos][3][3], rows a', b', c'), exactly as the kernels receive them. */
 xrt_status xrt_cell_mats(const xrt_crystal *xtal, double *host_out);

@@ -10,7 +10,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <climits>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -80,10 +82,15 @@ xrt_status check_detector(const xrt_detector *d)
     if (d->layer_dt == 0 && d->n_layers != 1)
         return fail(XRT_EINVAL, "layer_dt == 0 (no thickness model) requires n_layers == 1");
     if (!is_fin(d->atten_len) || d->atten_len <= 0) return fail(XRT_EINVAL, "atten_len must be finite and > 0");
-    if (d->roi_f0 < 0 || d->roi_f1 > d->n_fast || d->roi_f0 >= d->roi_f1 || d->roi_s0 < 0 ||
-        d->roi_s1 > d->n_slow || d->roi_s0 >= d->roi_s1)
-        return fail(XRT_EINVAL, "ROI [%d,%d)x[%d,%d) is empty or outside the %dx%d detector", d->roi_f0,
-                    d->roi_f1, d->roi_s0, d->roi_s1, d->n_fast, d->n_slow);
+    return XRT_OK;
+}
+
+xrt_status check_roi(const xrt_detector *d, int64_t f0, int64_t f1, int64_t s0, int64_t s1, int64_t k)
+{
+    if (f0 < 0 || f1 > d->n_fast || f0 >= f1 || s0 < 0 || s1 > d->n_slow || s0 >= s1)
+        return fail(XRT_EINVAL, "ROI %lld: [%lld,%lld)x[%lld,%lld) is empty or outside the %dx%d detector",
+                    (long long)k, (long long)f0, (long long)f1, (long long)s0, (long long)s1, d->n_fast,
+                    d->n_slow);
     return XRT_OK;
 }
 
@@ -171,6 +178,23 @@ void build_cell_mats(const xrt_crystal *x, double *out)
     }
 }
 
+// Rotations Q_{k,m} = umat_m R_k applied after U (for the adjoint:
+// h_i = (U a_i) . (Q^T S)).
+void build_rotations(const xrt_crystal *x, double *out)
+{
+    for (int k = 0; k < x->n_phi; ++k) {
+        double Rk[9];
+        rodrigues(x->spindle, x->phi0 + (double)k * x->dphi, Rk);
+        for (int m = 0; m < x->n_mos; ++m) {
+            const double *Um = x->umats + 9 * (size_t)m;
+            double *Q = out + 9 * ((size_t)k * x->n_mos + m);
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c)
+                    Q[3 * r + c] = (Um[3 * r] * Rk[c] + Um[3 * r + 1] * Rk[3 + c]) + Um[3 * r + 2] * Rk[6 + c];
+        }
+    }
+}
+
 // Source rows: direction, wavelength, weight and the polarization basis
 // e_perp = unit(evec - (evec . dir) dir), b = dir x e_perp.
 void build_sources(const xrt_beam *b, double *out)
@@ -214,12 +238,6 @@ void fill_params(const xrt_detector *d, const xrt_beam *b, const xrt_crystal *x,
     p.atten_len = d->atten_len;
     p.O = d->oversample;
     p.T = d->n_layers;
-    p.roi_f0 = d->roi_f0;
-    p.roi_s0 = d->roi_s0;
-    p.roi_nf = d->roi_f1 - d->roi_f0;
-    p.roi_ns = d->roi_s1 - d->roi_s0;
-    p.tiles_f = (p.roi_nf + 15) / 16;
-    p.n_tiles = p.tiles_f * ((p.roi_ns + 15) / 16);
     p.n_src = b->n_src;
     p.n_rot = x->n_phi * x->n_mos;
     p.shape = x->shape;
@@ -227,6 +245,8 @@ void fill_params(const xrt_detector *d, const xrt_beam *b, const xrt_crystal *x,
     for (int i = 0; i < 3; ++i) {
         p.N[i] = x->N[i];
         p.gk[i] = 2.0 * x->N[i] * x->N[i] / x->gauss_c;
+        p.m2gk[i] = -2.0 * p.gk[i];
+        p.inv2N[i] = 2.0 / x->N[i];
         ln += 2.0 * std::log(x->N[i]);
     }
     p.ln_n2 = ln;
@@ -263,11 +283,11 @@ double biased_zero_offset(const xrt_fhkl *t, int64_t esize)
 // vertex is within 90 degrees of dir_j, the cone of directions within the
 // largest vertex angle is convex and holds the whole box, so the vertices
 // bound the angle; otherwise |d - dir_j| <= 2.
-bool h_inside(const xrt_detector *d, const xrt_beam *b, const double *mats, size_t n_rot,
-              const xrt_fhkl *t)
+bool h_inside(const xrt_detector *d, const int64_t box[4], const xrt_beam *b, const double *mats,
+              size_t n_rot, const xrt_fhkl *t)
 {
-    double Fr[2] = {d->roi_f0 * d->pixel - d->beam_f, d->roi_f1 * d->pixel - d->beam_f};
-    double Sr[2] = {d->roi_s0 * d->pixel - d->beam_s, d->roi_s1 * d->pixel - d->beam_s};
+    double Fr[2] = {box[0] * d->pixel - d->beam_f, box[1] * d->pixel - d->beam_f};
+    double Sr[2] = {box[2] * d->pixel - d->beam_s, box[3] * d->pixel - d->beam_s};
     double Lr[2] = {d->distance, d->distance + (double)(d->n_layers - 1) * d->layer_dt};
     double smax = 0.0;
     for (int j = 0; j < b->n_src; ++j) {
@@ -379,30 +399,64 @@ xrt_status xrt_cell_mats(const xrt_crystal *xtal, double *host_out)
     return XRT_OK;
 }
 
-xrt_status xrt_simulate(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal,
-                        const xrt_fhkl *fhkl, int32_t precision, void *dev_image, int32_t out_dtype,
-                        int32_t accumulate, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Everything a launch over a list of equal-size regions of interest needs:
+// kernel parameters and the per-shot tables in one host buffer
+// [cell matrices | sources | ROI origins (int32 pairs) | rotations Q].
+struct Plan {
+    xrt::Params p;
+    std::vector<double> host;
+    size_t n_rot = 0, o_src = 0, o_orig = 0, o_q = 0;
+    bool clamp = true;
+};
+
+xrt_status make_plan(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal,
+                     const xrt_fhkl *fhkl, int64_t n_roi, const int32_t *origins, int32_t roi_nf,
+                     int32_t roi_ns, bool with_q, Plan &pl)
 {
     xrt_status st;
     if ((st = check_detector(det)) || (st = check_beam(beam)) || (st = check_crystal(xtal))) return st;
     if (!fhkl) return fail(XRT_EINVAL, "fhkl is NULL");
-    if (precision != XRT_FP64 && precision != XRT_MIXED) return fail(XRT_EINVAL, "unknown precision %d", precision);
-    if (out_dtype != XRT_F32 && out_dtype != XRT_F64) return fail(XRT_EINVAL, "unknown out_dtype %d", out_dtype);
-    if (accumulate != 0 && accumulate != 1) return fail(XRT_EINVAL, "accumulate must be 0 or 1");
-    if (!dev_image) return fail(XRT_EINVAL, "dev_image is NULL");
+    if (n_roi < 1 || n_roi > (1 << 22)) return fail(XRT_ERANGE, "n_roi must be in [1, 2^22]");
+    if (!origins) return fail(XRT_EINVAL, "ROI origins are NULL");
+    if (roi_nf < 1 || roi_ns < 1) return fail(XRT_EINVAL, "ROI size must be >= 1");
+    int64_t box[4] = {INT64_MAX, INT64_MIN, INT64_MAX, INT64_MIN};
+    for (int64_t k = 0; k < n_roi; ++k) {
+        const int64_t f0 = origins[2 * k], s0 = origins[2 * k + 1];
+        if ((st = check_roi(det, f0, f0 + roi_nf, s0, s0 + roi_ns, k))) return st;
+        box[0] = std::min(box[0], f0);
+        box[1] = std::max(box[1], f0 + roi_nf);
+        box[2] = std::min(box[2], s0);
+        box[3] = std::max(box[3], s0 + roi_ns);
+    }
+    const int64_t tiles_f = (roi_nf + 15) / 16, tiles_per = tiles_f * ((roi_ns + 15) / 16);
+    if (tiles_per * n_roi >= ((int64_t)1 << 31)) return fail(XRT_ERANGE, "too many tiles");
     int dev = -1;
     HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
     if (dev != fhkl->device)
         return fail(XRT_EINVAL, "fhkl lives on device %d, current device is %d", fhkl->device, dev);
 
-    const size_t n_rot = (size_t)xtal->n_phi * xtal->n_mos;
-    const size_t n_words = 9 * n_rot + xrt::SRC_STRIDE * (size_t)beam->n_src;
-    std::vector<double> host(n_words);
-    build_cell_mats(xtal, host.data());
-    build_sources(beam, host.data() + 9 * n_rot);
+    pl.n_rot = (size_t)xtal->n_phi * xtal->n_mos;
+    pl.o_src = 9 * pl.n_rot;
+    pl.o_orig = pl.o_src + xrt::SRC_STRIDE * (size_t)beam->n_src;
+    pl.o_q = pl.o_orig + (size_t)n_roi;  // one double slot holds one int32 pair
+    pl.host.assign(pl.o_q + (with_q ? 9 * pl.n_rot : 0), 0.0);
+    build_cell_mats(xtal, pl.host.data());
+    build_sources(beam, pl.host.data() + pl.o_src);
+    std::memcpy(pl.host.data() + pl.o_orig, origins, sizeof(int32_t) * 2 * (size_t)n_roi);
+    if (with_q) build_rotations(xtal, pl.host.data() + pl.o_q);
 
-    xrt::Params p;
+    xrt::Params &p = pl.p;
     fill_params(det, beam, xtal, p);
+    p.roi_nf = roi_nf;
+    p.roi_ns = roi_ns;
+    p.tiles_f = (int32_t)tiles_f;
+    p.tiles_per_roi = (int32_t)tiles_per;
+    p.n_roi = (int32_t)n_roi;
+    p.n_tiles = (int32_t)(tiles_per * n_roi);
     p.F2_64 = fhkl->F2_64;
     p.F2_32 = fhkl->F2_32;
     p.bytes64 = fhkl->bytes64;
@@ -417,23 +471,117 @@ xrt_status xrt_simulate(const xrt_detector *det, const xrt_beam *beam, const xrt
     p.sb4 = 4.0 * fhkl->sb;
     p.off8 = biased_zero_offset(fhkl, 8);
     p.off4 = biased_zero_offset(fhkl, 4);
-    const bool clamp = !h_inside(det, beam, host.data(), n_rot, fhkl);
-    p.image = dev_image;
-    p.out_f64 = out_dtype == XRT_F64;
-    p.accumulate = accumulate;
+    pl.clamp = !h_inside(det, box, beam, pl.host.data(), pl.n_rot, fhkl);
+    return XRT_OK;
+}
 
-    hipStream_t s = (hipStream_t)stream;
+// Points the parameters at the uploaded copy of the tables.
+void bind_tables(Plan &pl, double *dev)
+{
+    pl.p.mats = dev;
+    pl.p.src = dev + pl.o_src;
+    pl.p.origins = reinterpret_cast<const int32_t *>(dev + pl.o_orig);
+    pl.p.qmats = pl.host.size() > pl.o_q ? dev + pl.o_q : nullptr;
+}
+
+xrt_status check_call(int32_t precision, int32_t dtype, const void *ptr, const char *what)
+{
+    if (precision != XRT_FP64 && precision != XRT_MIXED) return fail(XRT_EINVAL, "unknown precision %d", precision);
+    if (dtype != XRT_F32 && dtype != XRT_F64) return fail(XRT_EINVAL, "unknown dtype %d", dtype);
+    if (!ptr) return fail(XRT_EINVAL, "%s is NULL", what);
+    return XRT_OK;
+}
+
+xrt_status run_spots(Plan &pl, int32_t precision, void *dev_image, int32_t out_dtype, int32_t accumulate,
+                     hipStream_t s, const char *who)
+{
+    pl.p.image = dev_image;
+    pl.p.out_f64 = out_dtype == XRT_F64;
+    pl.p.accumulate = accumulate;
     double *tables = nullptr;
-    HIP_TRY(hipMallocAsync((void **)&tables, sizeof(double) * n_words, s), "hipMallocAsync");
-    hipError_t e = hipMemcpyAsync(tables, host.data(), sizeof(double) * n_words, hipMemcpyHostToDevice, s);
+    const size_t bytes = sizeof(double) * pl.host.size();
+    HIP_TRY(hipMallocAsync((void **)&tables, bytes, s), "hipMallocAsync");
+    hipError_t e = hipMemcpyAsync(tables, pl.host.data(), bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
-        p.mats = tables;
-        p.src = tables + 9 * n_rot;
-        e = xrt::launch_spots(p, precision, clamp, s);
+        bind_tables(pl, tables);
+        e = xrt::launch_spots(pl.p, precision, pl.clamp, s);
     }
     hipError_t e2 = hipFreeAsync(tables, s);
-    if (e != hipSuccess) return hip_fail(e, "xrt_simulate");
-    if (e2 != hipSuccess) return hip_fail(e2, "xrt_simulate: hipFreeAsync");
+    if (e != hipSuccess) return hip_fail(e, who);
+    if (e2 != hipSuccess) return hip_fail(e2, who);
+    return XRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+xrt_status xrt_simulate(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal,
+                        const xrt_fhkl *fhkl, int32_t precision, void *dev_image, int32_t out_dtype,
+                        int32_t accumulate, void *stream)
+{
+    xrt_status st;
+    if ((st = check_call(precision, out_dtype, dev_image, "dev_image"))) return st;
+    if (accumulate != 0 && accumulate != 1) return fail(XRT_EINVAL, "accumulate must be 0 or 1");
+    if (!det) return fail(XRT_EINVAL, "detector is NULL");
+    if ((st = check_detector(det))) return st;
+    if ((st = check_roi(det, det->roi_f0, det->roi_f1, det->roi_s0, det->roi_s1, 0))) return st;
+    const int32_t origin[2] = {det->roi_f0, det->roi_s0};
+    Plan pl;
+    if ((st = make_plan(det, beam, xtal, fhkl, 1, origin, det->roi_f1 - det->roi_f0, det->roi_s1 - det->roi_s0,
+                        false, pl)))
+        return st;
+    return run_spots(pl, precision, dev_image, out_dtype, accumulate, (hipStream_t)stream, "xrt_simulate");
+}
+
+xrt_status xrt_simulate_rois(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal,
+                             const xrt_fhkl *fhkl, int32_t precision, int64_t n_roi,
+                             const int32_t *host_origins, int32_t roi_nf, int32_t roi_ns, void *dev_images,
+                             int32_t out_dtype, void *stream)
+{
+    xrt_status st;
+    if ((st = check_call(precision, out_dtype, dev_images, "dev_images"))) return st;
+    Plan pl;
+    if ((st = make_plan(det, beam, xtal, fhkl, n_roi, host_origins, roi_nf, roi_ns, false, pl))) return st;
+    return run_spots(pl, precision, dev_images, out_dtype, 0, (hipStream_t)stream, "xrt_simulate_rois");
+}
+
+xrt_status xrt_backward_rois(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal,
+                             const xrt_fhkl *fhkl, int32_t precision, int64_t n_roi,
+                             const int32_t *host_origins, int32_t roi_nf, int32_t roi_ns,
+                             const void *dev_dLdI, int32_t dLdI_dtype, double *dev_grad13, void *stream)
+{
+    xrt_status st;
+    if ((st = check_call(precision, dLdI_dtype, dev_dLdI, "dev_dLdI"))) return st;
+    if (!dev_grad13) return fail(XRT_EINVAL, "dev_grad13 is NULL");
+    if (xtal && xtal->struct_size == sizeof(xrt_crystal) && xtal->shape != XRT_SHAPE_GAUSS)
+        return fail(XRT_EINVAL, "the adjoint is defined for the Gaussian shape only");
+    Plan pl;
+    if ((st = make_plan(det, beam, xtal, fhkl, n_roi, host_origins, roi_nf, roi_ns, true, pl))) return st;
+    if (xtal->scale == 0.0) return fail(XRT_EINVAL, "scale must be nonzero for its gradient");
+    for (int i = 0; i < 9; ++i) pl.p.m0[i] = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        double v[3];
+        matvec(xtal->U, xtal->cell + 3 * i, v);
+        for (int c = 0; c < 3; ++c) pl.p.m0[3 * i + c] = v[c];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t tb = sizeof(double) * pl.host.size();
+    const size_t pb = sizeof(double) * 13 * (size_t)pl.p.n_tiles;
+    double *tables = nullptr, *partial = nullptr;
+    HIP_TRY(hipMallocAsync((void **)&tables, tb, s), "hipMallocAsync");
+    hipError_t e = hipMallocAsync((void **)&partial, pb, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(tables, pl.host.data(), tb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        bind_tables(pl, tables);
+        e = xrt::launch_grad(pl.p, precision, pl.clamp, dev_dLdI, dLdI_dtype == XRT_F64, partial, dev_grad13,
+                             1.0 / xtal->scale, s);
+    }
+    hipError_t e2 = hipFreeAsync(tables, s);
+    hipError_t e3 = partial ? hipFreeAsync(partial, s) : hipSuccess;
+    if (e != hipSuccess) return hip_fail(e, "xrt_backward_rois");
+    if (e2 != hipSuccess) return hip_fail(e2, "xrt_backward_rois");
+    if (e3 != hipSuccess) return hip_fail(e3, "xrt_backward_rois");
     return XRT_OK;
 }
 

@@ -33,8 +33,10 @@ struct Params {
     double fdet[3], sdet[3], odet[3];
     double layer_dt, atten_len;
     int32_t O, T;
-    int32_t roi_f0, roi_s0, roi_nf, roi_ns;
-    int32_t tiles_f, n_tiles;
+    // regions of interest: n_roi rectangles of roi_nf x roi_ns pixels with
+    // origins (i_f, i_s) in `origins`; each is cut into 16 x 16 tiles
+    int32_t roi_nf, roi_ns;
+    int32_t tiles_f, tiles_per_roi, n_roi, n_tiles;
     // loop extents
     int32_t n_src, n_rot;
     // lattice
@@ -57,6 +59,11 @@ struct Params {
     // per-shot tables in device memory
     const double *mats;    // [n_rot][9]
     const double *src;     // [n_src][SRC_STRIDE]
+    const int32_t *origins;  // [n_roi][2]
+    const double *qmats;   // [n_rot][9] rotations umat_m R_k (adjoint only)
+    double m0[9];          // rows U a_i (adjoint only)
+    double m2gk[3];        // -2 gk_i (adjoint only)
+    double inv2N[3];       // 2 / N_i (adjoint only)
     // output
     void *image;
     int32_t out_f64;
@@ -68,6 +75,10 @@ hipError_t launch_spots(const Params &p, int precision, bool clamp, hipStream_t 
 hipError_t launch_pad_table(const void *src, int src_f64, int32_t na, int32_t nb, int32_t nc,
                             int32_t pad, double F_default, double *F2_64, float *F2_32,
                             hipStream_t stream);
+// Adjoint: partial sums per tile into partial[n_tiles][13], then one
+// fixed-order reduction into grad13 (component 12 scaled by inv_scale).
+hipError_t launch_grad(const Params &p, int precision, bool clamp, const void *dLdI, int dLdI_f64,
+                       double *partial, double *grad13, double inv_scale, hipStream_t stream);
 hipError_t launch_trace(const Params &p, int64_t n, const int32_t *idx, double *S, double *h,
                         hipStream_t stream);
 

@@ -227,20 +227,38 @@ __device__ __forceinline__ int xcd_tile(int bid, int n_tiles)
     return x * q + (x < r ? x : r) + k;
 }
 
+// The pixel of this lane: workgroup -> (ROI, tile) through the XCD banding,
+// lane -> 8 x 8 block of its wave.  Lanes past a ROI edge trace the ROI's
+// last valid pixel (so loops stay uniform) and store nothing.
+struct Pixel {
+    int i_f, i_s;
+    bool live;
+    size_t out;  // element index in the [n_roi][roi_ns][roi_nf] output
+};
+
+__device__ __forceinline__ Pixel tile_pixel(const Params &p)
+{
+    const int tile = xcd_tile(blockIdx.x, p.n_tiles);
+    const int roi = tile / p.tiles_per_roi, t = tile - roi * p.tiles_per_roi;
+    const int tf = t % p.tiles_f, ts = t / p.tiles_f;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lf = tf * TILE + (wave & 1) * 8 + (lane & 7);
+    const int ls = ts * TILE + (wave >> 1) * 8 + (lane >> 3);
+    Pixel px;
+    px.live = lf < p.roi_nf && ls < p.roi_ns;
+    px.i_f = p.origins[2 * roi] + (lf < p.roi_nf ? lf : p.roi_nf - 1);
+    px.i_s = p.origins[2 * roi + 1] + (ls < p.roi_ns ? ls : p.roi_ns - 1);
+    px.out = ((size_t)roi * p.roi_ns + ls) * p.roi_nf + lf;
+    return px;
+}
+
 template <int PREC, int SHAPE, bool CLAMP>
 __global__ __launch_bounds__(BLOCK) void spots_kernel(const Params p)
 {
     const __amdgpu_buffer_rsrc_t tab = PREC == XRT_FP64 ? table_rsrc(p.F2_64, p.bytes64)
                                                          : table_rsrc(p.F2_32, p.bytes32);
-    const int tile = xcd_tile(blockIdx.x, p.n_tiles);
-    const int tf = tile % p.tiles_f, ts = tile / p.tiles_f;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int lf = tf * TILE + (wave & 1) * 8 + (lane & 7);
-    const int ls = ts * TILE + (wave >> 1) * 8 + (lane >> 3);
-    const bool live = lf < p.roi_nf && ls < p.roi_ns;
-    // lanes past the ROI edge trace the last valid pixel and do not store
-    const int i_f = p.roi_f0 + (lf < p.roi_nf ? lf : p.roi_nf - 1);
-    const int i_s = p.roi_s0 + (ls < p.roi_ns ? ls : p.roi_ns - 1);
+    const Pixel px = tile_pixel(p);
+    const int i_f = px.i_f, i_s = px.i_s;
 
     double acc64 = 0.0;
     float acc = 0.0f, accc = 0.0f;
@@ -274,9 +292,9 @@ __global__ __launch_bounds__(BLOCK) void spots_kernel(const Params p)
                     }
                 }
             }
-    if (!live) return;
+    if (!px.live) return;
     const double val = p.norm * (PREC == XRT_FP64 ? acc64 : (double)(acc - accc));
-    const size_t o = (size_t)ls * p.roi_nf + lf;
+    const size_t o = px.out;
     if (p.out_f64) {
         double *img = (double *)p.image;
         img[o] = p.accumulate ? img[o] + val : val;
@@ -309,6 +327,172 @@ hipError_t launch_spots(const Params &p, int precision, bool clamp, hipStream_t 
         else
             launch_one<XRT_MIXED, XRT_SHAPE_GAUSS>(p, clamp, stream);
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the Gaussian-shape sum (the refinement of per-crystal parameters
+// against measured images, paper section II).  With g_p = dL/dI_p given, it
+// accumulates over every term of every pixel
+//   dL/dM0_{i,c} = sum g_p K w P dOmega C F^2 dL2/dh_i (Q^T S)_c,
+//   dL/dN_i      = sum g_p K w P dOmega C F^2 dL2/dN_i,
+//   dL/dscale    = sum g_p I_p / scale,
+// where h_i = M0_i . (Q^T S), Q = umat_m R_k, L2 = prod N_i^2
+// exp(-gk_i f_i^2) with gk_i = 2 N_i^2 / c, dL2/dh_i = -2 gk_i f_i L2 and
+// dL2/dN_i = (2/N_i) (1 - gk_i f_i^2) L2.  Each lane owns a pixel; the 13
+// sums are reduced over the workgroup by a fixed tree and then over the
+// workgroups by a fixed-order kernel, so the result is deterministic.
+// ---------------------------------------------------------------------------
+template <bool CLAMP>
+__device__ __forceinline__ void grad_term_f64(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *Q,
+                                              const double S[3], double w, double acc[13])
+{
+    double Sp[3], hr[3], f[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Sp[c] = __builtin_fma(Q[6 + c], S[2], __builtin_fma(Q[3 + c], S[1], Q[c] * S[0]));
+    double e = p.ln_n2;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double h = __builtin_fma(p.m0[3 * i + 2], Sp[2], __builtin_fma(p.m0[3 * i + 1], Sp[1], p.m0[3 * i] * Sp[0]));
+        hr[i] = __builtin_rint(h);
+        f[i] = h - hr[i];
+        e = __builtin_fma(-p.gk[i], f[i] * f[i], e);
+    }
+    const double base = w * load_f64(tab, table_offset<CLAMP>(p, hr, p.sa8, p.sb8, 8.0, p.off8)) * exp(e);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double dh = base * p.m2gk[i] * f[i];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[3 * i + c] = __builtin_fma(dh, Sp[c], acc[3 * i + c]);
+        acc[9 + i] = __builtin_fma(base * p.inv2N[i], __builtin_fma(-p.gk[i], f[i] * f[i], 1.0), acc[9 + i]);
+    }
+    acc[12] += base;
+}
+
+// Mixed: Q^T S, h and f in binary64; the exponent, the lattice factor and the
+// products in binary32 (partial sums over the domain loop in binary32, then
+// binary64).
+template <bool CLAMP>
+__device__ __forceinline__ void grad_term_mixed(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *Q,
+                                                const double S[3], float w, float acc[13])
+{
+    double Sp[3], hr[3];
+    float f[3], Sf[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Sp[c] = __builtin_fma(Q[6 + c], S[2], __builtin_fma(Q[3 + c], S[1], Q[c] * S[0]));
+        Sf[c] = (float)Sp[c];
+    }
+    float e = (float)p.ln_n2;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double h = __builtin_fma(p.m0[3 * i + 2], Sp[2], __builtin_fma(p.m0[3 * i + 1], Sp[1], p.m0[3 * i] * Sp[0]));
+        hr[i] = __builtin_rint(h);
+        f[i] = (float)(h - hr[i]);
+        e = __builtin_fmaf(-(float)p.gk[i], f[i] * f[i], e);
+    }
+    const float base = w * load_f32(tab, table_offset<CLAMP>(p, hr, p.sa4, p.sb4, 4.0, p.off4)) * __expf(e);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float dh = base * (float)p.m2gk[i] * f[i];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[3 * i + c] = __builtin_fmaf(dh, Sf[c], acc[3 * i + c]);
+        acc[9 + i] = __builtin_fmaf(base * (float)p.inv2N[i], __builtin_fmaf(-(float)p.gk[i], f[i] * f[i], 1.0f),
+                                    acc[9 + i]);
+    }
+    acc[12] += base;
+}
+
+// Sum of v over the 256 lanes of a workgroup by a fixed tree: xor-shuffles
+// within each wave, then the four wave sums in order.  Valid in lane 0.
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    return (lds[0] + lds[1]) + (lds[2] + lds[3]);
+}
+
+template <int PREC, bool CLAMP>
+__global__ __launch_bounds__(BLOCK) void grad_kernel(const Params p, const void *dLdI, int dLdI_f64,
+                                                     double *partial)
+{
+    __shared__ double lds[4];
+    const __amdgpu_buffer_rsrc_t tab = PREC == XRT_FP64 ? table_rsrc(p.F2_64, p.bytes64)
+                                                         : table_rsrc(p.F2_32, p.bytes32);
+    const Pixel px = tile_pixel(p);
+    double gp = 0.0;
+    if (px.live) gp = dLdI_f64 ? ((const double *)dLdI)[px.out] : (double)((const float *)dLdI)[px.out];
+    double acc[13];
+#pragma unroll
+    for (int c = 0; c < 13; ++c) acc[c] = 0.0;
+    for (int u = 0; u < p.O; ++u)
+        for (int v = 0; v < p.O; ++v)
+            for (int t = 0; t < p.T; ++t) {
+                double d[3], R;
+                sample_dir(p, px.i_f, px.i_s, u, v, t, d, R);
+                const double wgeo = gp * p.norm * sample_weight(p, d, R, t);
+                for (int j = 0; j < p.n_src; ++j) {
+                    const double *src = p.src + SRC_STRIDE * j;
+                    double S[3];
+                    scatter(src, d, S);
+                    const double w = src[SRC_WEIGHT] * polarization(src, d, p.kahn) * wgeo;
+                    if (PREC == XRT_FP64) {
+                        for (int r = 0; r < p.n_rot; ++r) grad_term_f64<CLAMP>(p, tab, p.qmats + 9 * r, S, w, acc);
+                    } else {
+                        float a32[13];
+#pragma unroll
+                        for (int c = 0; c < 13; ++c) a32[c] = 0.0f;
+                        for (int r = 0; r < p.n_rot; ++r)
+                            grad_term_mixed<CLAMP>(p, tab, p.qmats + 9 * r, S, (float)w, a32);
+#pragma unroll
+                        for (int c = 0; c < 13; ++c) acc[c] += (double)a32[c];
+                    }
+                }
+            }
+    for (int c = 0; c < 13; ++c) {
+        const double s = block_sum(acc[c], lds);
+        if (threadIdx.x == 0) partial[13 * (size_t)blockIdx.x + c] = s;
+    }
+}
+
+// grad13[c] = sum over workgroups b of partial[b][c], in a fixed order: lane t
+// adds b = t, t + 256, ... sequentially, then the fixed block tree.
+__global__ __launch_bounds__(BLOCK) void grad_reduce_kernel(const double *partial, int n_blocks, double *grad13,
+                                                            double inv_scale)
+{
+    __shared__ double lds[4];
+    for (int c = 0; c < 13; ++c) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < n_blocks; b += BLOCK) v += partial[13 * (size_t)b + c];
+        const double s = block_sum(v, lds);
+        if (threadIdx.x == 0) grad13[c] = c == 12 ? s * inv_scale : s;
+    }
+}
+
+template <int PREC>
+static void launch_grad_one(const Params &p, bool clamp, const void *dLdI, int f64, double *partial,
+                            hipStream_t stream)
+{
+    if (clamp)
+        hipLaunchKernelGGL((grad_kernel<PREC, true>), dim3(p.n_tiles), dim3(BLOCK), 0, stream, p, dLdI, f64, partial);
+    else
+        hipLaunchKernelGGL((grad_kernel<PREC, false>), dim3(p.n_tiles), dim3(BLOCK), 0, stream, p, dLdI, f64, partial);
+}
+
+hipError_t launch_grad(const Params &p, int precision, bool clamp, const void *dLdI, int dLdI_f64,
+                       double *partial, double *grad13, double inv_scale, hipStream_t stream)
+{
+    if (precision == XRT_FP64)
+        launch_grad_one<XRT_FP64>(p, clamp, dLdI, dLdI_f64, partial, stream);
+    else
+        launch_grad_one<XRT_MIXED>(p, clamp, dLdI, dLdI_f64, partial, stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3(1), dim3(BLOCK), 0, stream, partial, p.n_tiles, grad13, inv_scale);
     return hipGetLastError();
 }
 

@@ -78,7 +78,8 @@ _lib = None
 
 #: every entry point of include/xrt.h
 SYMBOLS = ("xrt_version", "xrt_last_error", "xrt_fhkl_create", "xrt_fhkl_destroy",
-           "xrt_simulate", "xrt_cell_mats", "xrt_trace_terms")
+           "xrt_simulate", "xrt_simulate_rois", "xrt_backward_rois", "xrt_cell_mats",
+           "xrt_trace_terms")
 
 
 def load():
@@ -95,6 +96,12 @@ def load():
     lib.xrt_fhkl_destroy.argtypes = [C.c_void_p]
     lib.xrt_simulate.argtypes = [C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal), C.c_void_p,
                                  C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
+    lib.xrt_simulate_rois.argtypes = [C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal), C.c_void_p,
+                                      C.c_int32, C.c_int64, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                      C.c_int32, C.c_void_p]
+    lib.xrt_backward_rois.argtypes = [C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal), C.c_void_p,
+                                      C.c_int32, C.c_int64, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                      C.c_int32, C.c_void_p, C.c_void_p]
     lib.xrt_cell_mats.argtypes = [C.POINTER(Crystal), C.c_void_p]
     lib.xrt_trace_terms.argtypes = [C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal), C.c_int64,
                                     C.c_void_p, C.c_void_p, C.c_void_p]
@@ -206,6 +213,59 @@ def simulate(shot, fhkl: Fhkl, precision="fp64", out=None, out_dtype=None, accum
                                _PREC[precision], C.c_void_p(out.data_ptr()), dt, int(bool(accumulate)),
                                _stream(stream)))
     return out
+
+
+def _origins(origins):
+    o = _arr(origins, np.int32)
+    if o.ndim != 2 or o.shape[1] != 2:
+        raise ValueError("origins must be (n_roi, 2) int32 (i_f, i_s)")
+    return o
+
+
+_DT = {}
+
+
+def _dtype_code(t):
+    import torch
+    return {torch.float32: XRT_F32, torch.float64: XRT_F64}[t.dtype]
+
+
+def simulate_rois(shot, fhkl: Fhkl, origins, roi_size, precision="fp64", out=None, out_dtype=None,
+                  stream=None):
+    """xrt_simulate_rois: images of n_roi regions (roi_size = (nf, ns)) with
+    the given (i_f, i_s) origins, as a [n_roi, ns, nf] tensor."""
+    import torch
+    st = ShotStructs(shot)
+    o = _origins(origins)
+    nf, ns = roi_size
+    if out is None:
+        if out_dtype is None:
+            out_dtype = torch.float64 if precision == "fp64" else torch.float32
+        out = torch.empty((len(o), ns, nf), dtype=out_dtype, device="cuda")
+    if tuple(out.shape) != (len(o), ns, nf) or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError(f"out must be a contiguous GPU tensor of shape {(len(o), ns, nf)}")
+    _check(load().xrt_simulate_rois(C.byref(st.det), C.byref(st.beam), C.byref(st.xtal), fhkl.handle,
+                                    _PREC[precision], len(o), o.ctypes.data, int(nf), int(ns),
+                                    C.c_void_p(out.data_ptr()), _dtype_code(out), _stream(stream)))
+    return out
+
+
+def backward_rois(shot, fhkl: Fhkl, origins, roi_size, dLdI, precision="fp64", grad=None, stream=None):
+    """xrt_backward_rois: 13 binary64 values dL/dM0 (9), dL/dN (3), dL/dscale
+    for the Gaussian shape, as a GPU tensor."""
+    import torch
+    st = ShotStructs(shot)
+    o = _origins(origins)
+    nf, ns = roi_size
+    if tuple(dLdI.shape) != (len(o), ns, nf) or not dLdI.is_contiguous() or not dLdI.is_cuda:
+        raise ValueError(f"dLdI must be a contiguous GPU tensor of shape {(len(o), ns, nf)}")
+    if grad is None:
+        grad = torch.empty(13, dtype=torch.float64, device="cuda")
+    _check(load().xrt_backward_rois(C.byref(st.det), C.byref(st.beam), C.byref(st.xtal), fhkl.handle,
+                                    _PREC[precision], len(o), o.ctypes.data, int(nf), int(ns),
+                                    C.c_void_p(dLdI.data_ptr()), _dtype_code(dLdI),
+                                    C.c_void_p(grad.data_ptr()), _stream(stream)))
+    return grad
 
 
 def cell_mats(shot) -> np.ndarray:

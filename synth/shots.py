@@ -324,3 +324,53 @@ def micro_shot(seed: int = 10, shape: int = SHAPE_SINCG) -> Shot:
         N=np.array([3.0, 4.0, 5.0]), shape=shape,
         hkl_min=np.array([-4, -4, -4]), F=F, F_default=7.0,
     )
+
+
+def roi_shot(seed: int = 5, n_roi: int = 512, size: int = 32, lam0: float = 1.30):
+    """The full-size crystal with the Gaussian shape (N = 20) and n_roi
+    non-overlapping size x size regions of interest around its predicted
+    Bragg spots: for every tabulated reflection the scattering vector
+    S = (M0^T)^-1 h (M0 rows = U a, U b, U c) is tested against the Ewald
+    sphere of lam0; the diffracted ray d = unit(S + z/lam0) is cut with the
+    detector plane; spots are ranked by F^2 exp(-eps^2 / (2 sigma^2)) with eps
+    the distance to the sphere and sigma = sqrt(c/2) / (N |a|) (the Gaussian's
+    width in reciprocal space).  Returns (shot, origins[n_roi, 2] int32)."""
+    shot = full_shot(seed=2, shape=SHAPE_GAUSS, N=20.0)
+    M0 = shot.U @ shot.cell.T                      # columns U a_i
+    B = np.linalg.inv(M0.T)                        # S = B h
+    n = shot.F.shape[0] // 2
+    r = np.arange(-n, n + 1)
+    H = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3).astype(np.float64)
+    F = shot.F.reshape(-1)
+    S = H @ B.T
+    kout = S + np.array([0.0, 0.0, 1.0 / lam0])
+    knorm = np.linalg.norm(kout, axis=1)
+    eps = knorm - 1.0 / lam0
+    sigma = math.sqrt(shot.gauss_c / 2.0) / (shot.N[0] * np.linalg.norm(shot.cell[0]))
+    keep = np.abs(eps) < 6 * sigma
+    d = kout[keep] / knorm[keep, None]
+    score = (F[keep] ** 2) * np.exp(-eps[keep] ** 2 / (2 * sigma * sigma))
+    fwd = d[:, 2] > 1e-3
+    d, score = d[fwd], score[fwd]
+    x = d[:, 0] * shot.distance / d[:, 2]
+    y = d[:, 1] * shot.distance / d[:, 2]
+    i_f = (x + shot.beam_f) / shot.pixel
+    i_s = (y + shot.beam_s) / shot.pixel
+    half = size // 2
+    on = (i_f >= half) & (i_f < shot.n_fast - half) & (i_s >= half) & (i_s < shot.n_slow - half)
+    order = np.argsort(-score[on], kind="stable")
+    cf, cs = i_f[on][order], i_s[on][order]
+    chosen = []
+    occupied = []
+    for fx, sx in zip(cf, cs):
+        f0 = int(math.floor(fx)) - half
+        s0 = int(math.floor(sx)) - half
+        if any(abs(f0 - a) < size and abs(s0 - b) < size for a, b in occupied):
+            continue
+        occupied.append((f0, s0))
+        chosen.append((f0, s0))
+        if len(chosen) == n_roi:
+            break
+    if len(chosen) < n_roi:
+        raise ValueError(f"only {len(chosen)} non-overlapping spots found")
+    return shot, np.array(chosen, dtype=np.int32)
