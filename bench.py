@@ -151,6 +151,34 @@ def adjoint_bench(steps):
     return out
 
 
+def serving_bench(n_cap=60, n_open=150, load=0.8):
+    """The served shot stream: independent shots with a random orientation,
+    log-uniform ROI (64..2463 x 64..2527 px), 1-100 sources, 1-200 domains,
+    N in [5, 40], the full-size detector and shared table, mixed precision.
+    Closed loop (all submitted at once) gives the capacity; then Poisson
+    arrivals at `load` x capacity give the latency percentiles."""
+    import numpy as np
+    import synth
+    from paper_2205_07976_amd import serve, xrt
+    base = synth.full_shot()
+    fh = xrt.Fhkl.from_shot(base)
+    rng = np.random.default_rng(4)
+    cap_shots = [synth.served_shot(rng, base.F, base.hkl_min) for _ in range(n_cap)]
+    open_shots = [synth.served_shot(rng, base.F, base.hkl_min) for _ in range(n_open)]
+    srv = xrt.Server(fh, hbm_budget=16 << 30, max_resident=64, precision="mixed")
+    # warm-up: the persistent kernel's first launch
+    serve.run_stream(srv, cap_shots[:2], np.zeros(2))
+    closed = serve.summarize(serve.run_stream(srv, cap_shots, np.zeros(n_cap)), cap_shots)
+    rate = load * closed["images_per_s"]
+    arr = serve.poisson_arrivals(np.random.default_rng(6), n_open, rate)
+    opened = serve.summarize(serve.run_stream(srv, open_shots, arr), open_shots, rate)
+    srv.close()
+    log(f"serving: capacity {closed['images_per_s']:.1f} img/s ({closed['Gterm_per_s']:.0f} Gterm/s); "
+        f"at {load:.2f} load p50 {opened['p50_ms']:.1f} ms p99 {opened['p99_ms']:.1f} ms")
+    return {"workload": "served stream: log-uniform ROI, 1-100 sources, 1-200 domains, N in [5,40], mixed",
+            "closed_loop": closed, "poisson": opened, "load": load}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +187,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the regions-of-interest adjoint")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served shot stream")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="finish with one device-to-device copy of this many MiB (a kernel of known "
                          "traffic that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -212,6 +241,11 @@ def main():
 
     if not args.no_adjoint:
         res["adjoint"] = adjoint_bench(args.steps)
+
+    if not args.no_serve:
+        res["serving"] = serving_bench()
+        res["p50_shot_latency_ms"] = res["serving"]["poisson"]["p50_ms"]
+        res["p99_shot_latency_ms"] = res["serving"]["poisson"]["p99_ms"]
 
     if args.copy_mib:
         n = args.copy_mib * (1 << 20) // 4

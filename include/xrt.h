@@ -211,6 +211,81 @@ xrt_status xrt_backward_rois(const xrt_detector *det, const xrt_beam *beam,
                              int32_t roi_ns, const void *dev_dLdI,
                              int32_t dLdI_dtype, double *dev_grad13, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of independent shots on one device.
+ *
+ * The paper runs many simulations per GPU and lets several producers share a
+ * GPU to hide latency (section IV, ranks per GPU).  A server owns one arena of
+ * device memory (its HBM budget, holding the images) and the structure
+ * factors (shared by every shot); shot descriptors and tables sit in pinned
+ * host memory that the kernel reads directly.  Submitted shots wait in
+ * arrival order; a shot is admitted when its image fits in the arena and a
+ * resident slot is free; the tiles of admitted shots are fed, round-robin in
+ * chunks, to a persistent kernel that keeps running while new shots join.  Every pixel is
+ * computed exactly as by xrt_simulate with the server's precision, so a shot's
+ * image is bit-identical whatever else runs beside it.
+ * Calls on one server are serialised internally; progress is driven by
+ * xrt_server_progress (call it often: it admits, publishes, launches and
+ * collects).  Limits per served shot: n_phi*n_mos <= 256, n_src <= 128.
+ * --------------------------------------------------------------------------- */
+typedef struct xrt_server xrt_server;
+
+typedef struct xrt_server_desc {
+    uint32_t struct_size;
+    uint64_t hbm_budget;    /* arena bytes, in [1 MiB, 1 TiB] */
+    int32_t max_resident;   /* shots admitted at once, in [1, 65536] */
+    int32_t precision;      /* XRT_FP64 or XRT_MIXED */
+    int32_t shape;          /* XRT_SHAPE_* of every served shot */
+    int32_t out_dtype;      /* XRT_F32 or XRT_F64 images */
+    int32_t workgroups;     /* persistent workgroups; 0 = 2 per compute unit,
+                               which leaves room on every unit for other work */
+    double idle_exit_us;    /* a workgroup without work for this long exits,
+                               in [1, 1e6]; the next progress call relaunches */
+} xrt_server_desc;
+
+enum { XRT_SHOT_QUEUED = 0, XRT_SHOT_RUNNING = 1, XRT_SHOT_DONE = 2 };
+
+typedef struct xrt_shot_info {
+    uint32_t struct_size;
+    int32_t state;          /* XRT_SHOT_* */
+    uint64_t image_bytes;
+    int32_t roi_nf, roi_ns; /* image is [roi_ns][roi_nf] */
+    double t_submit;        /* seconds since the server was created */
+    double t_admit;         /* -1 until admitted */
+    double t_done;          /* -1 until a progress call has seen it finish */
+} xrt_shot_info;
+
+/* Create a server on the current device; fhkl must outlive it.
+ * Errors: EINVAL/ERANGE/EVERSION on the descriptor, ENOMEM, EDEVICE. */
+xrt_status xrt_server_create(const xrt_server_desc *desc, const xrt_fhkl *fhkl,
+                             xrt_server **out);
+
+/* Stop the persistent kernel (it finishes its current chunks), wait for it and
+ * free everything; images of unreleased shots become invalid.  NULL is
+ * accepted. */
+xrt_status xrt_server_destroy(xrt_server *srv);
+
+/* Validate and queue one shot (the detector's ROI); copies every host array,
+ * never blocks.  ERANGE if the shot exceeds the served limits or can never
+ * fit the budget. */
+xrt_status xrt_server_submit(xrt_server *srv, const xrt_detector *det,
+                             const xrt_beam *beam, const xrt_crystal *xtal,
+                             uint64_t *ticket);
+
+/* Admit, upload, publish, launch and collect; *n_done receives the number of
+ * shots seen finishing during this call (may be NULL). */
+xrt_status xrt_server_progress(xrt_server *srv, int32_t *n_done);
+
+/* State and times of a shot.  info->struct_size must be set. */
+xrt_status xrt_server_info(xrt_server *srv, uint64_t ticket, xrt_shot_info *info);
+
+/* Device pointer of a finished shot's image inside the arena, valid until
+ * xrt_server_release.  EBUSY if not done. */
+xrt_status xrt_server_image(xrt_server *srv, uint64_t ticket, const void **dev_image);
+
+/* Free a finished shot's memory and slot.  EBUSY if not done. */
+xrt_status xrt_server_release(xrt_server *srv, uint64_t ticket);
+
 /* Diagnostics: the library's lab-frame cell matrices M_{k,m} (host output,
  * [n_phi*n_mos][3][3], rows a', b', c'), exactly as the kernels receive them. */
 xrt_status xrt_cell_mats(const xrt_crystal *xtal, double *host_out);

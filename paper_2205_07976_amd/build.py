@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libxrt.so")
-SOURCES = [os.path.join(CSRC, "xrt_kernels.hip"), os.path.join(CSRC, "xrt_api.cpp")]
+SOURCES = [os.path.join(CSRC, "xrt_kernels.hip"), os.path.join(CSRC, "xrt_api.cpp"),
+           os.path.join(CSRC, "xrt_server.cpp")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -17,13 +17,16 @@
 #include <vector>
 
 #include "../../include/xrt.h"
+#include "xrt_host.h"
 #include "xrt_internal.h"
 
 namespace {
-
 thread_local std::string g_err;
+}
 
-xrt_status fail(xrt_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+namespace xrt {
+namespace host {
+
 xrt_status fail(xrt_status code, const char *fmt, ...)
 {
     char buf[512];
@@ -41,6 +44,14 @@ xrt_status hip_fail(hipError_t e, const char *what)
         return fail(XRT_ENOMEM, "%s: %s", what, hipGetErrorString(e));
     return fail(XRT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
+
+}  // namespace host
+}  // namespace xrt
+
+namespace {
+
+using xrt::host::fail;
+using xrt::host::hip_fail;
 
 #define HIP_TRY(call, what)                      \
     do {                                         \
@@ -513,6 +524,45 @@ xrt_status run_spots(Plan &pl, int32_t precision, void *dev_image, int32_t out_d
 }
 
 }  // namespace
+
+namespace xrt {
+namespace host {
+
+xrt_status check_shot(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal)
+{
+    xrt_status st;
+    if ((st = check_detector(det)) || (st = check_beam(beam)) || (st = check_crystal(xtal))) return st;
+    return check_roi(det, det->roi_f0, det->roi_f1, det->roi_s0, det->roi_s1, 0);
+}
+
+xrt_status served_descriptor(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal,
+                             const xrt_fhkl *fhkl, int32_t out_dtype, ShotDesc *d, std::vector<double> &tables)
+{
+    const int32_t origin[2] = {det->roi_f0, det->roi_s0};
+    Plan pl;
+    xrt_status st = make_plan(det, beam, xtal, fhkl, 1, origin, det->roi_f1 - det->roi_f0,
+                              det->roi_s1 - det->roi_s0, false, pl);
+    if (st) return st;
+    std::memset(d, 0, sizeof *d);
+    d->p = pl.p;
+    d->p.out_f64 = out_dtype == XRT_F64;
+    d->roi_f0 = det->roi_f0;
+    d->roi_s0 = det->roi_s0;
+    d->clamp = pl.clamp ? 1 : 0;
+    tables.assign(pl.host.begin(), pl.host.begin() + (ptrdiff_t)pl.o_orig);
+    return XRT_OK;
+}
+
+void fhkl_tables(const xrt_fhkl *t, const double **F2_64, const float **F2_32, uint32_t *bytes64, uint32_t *bytes32)
+{
+    *F2_64 = t->F2_64;
+    *F2_32 = t->F2_32;
+    *bytes64 = t->bytes64;
+    *bytes32 = t->bytes32;
+}
+
+}  // namespace host
+}  // namespace xrt
 
 extern "C" {
 

@@ -70,6 +70,60 @@ struct Params {
     int32_t accumulate;
 };
 
+// ---------------------------------------------------------------------------
+// Served shots.  A served shot's descriptor and tables live in a pinned host
+// arena (written by the host, read by the kernel with range-checked loads, so
+// admitting a shot needs no copy on the device); its image lives in the
+// device arena, the server's HBM budget.  Work is published as chunks of
+// tiles in a ring in pinned host memory.
+// ---------------------------------------------------------------------------
+constexpr int SERVE_MAX_ROT = 256;   // spindle steps x mosaic domains per served shot
+constexpr int SERVE_MAX_SRC = 128;   // sources per served shot
+constexpr int SERVE_MAX_CHUNK = 64;  // tiles per chunk
+
+struct ShotDesc {
+    Params p;               // pointer fields unused
+    uint64_t mats_rel;      // byte offsets of the tables relative to this descriptor
+    uint64_t src_rel;
+    uint64_t image_off;     // byte offset of the image in the device arena
+    uint64_t image_bytes;
+    int32_t roi_f0, roi_s0;
+    int32_t clamp;
+    int32_t pad;
+};
+
+struct ServeChunk {         // written by the host before the tail publishes it
+    uint64_t desc_off;      // byte offset of the ShotDesc in the host arena
+    int32_t tile0, n_tiles;
+    uint32_t seq1;          // chunk number + 1: the value its done flag takes
+    uint32_t pad;
+};
+
+struct ServeCtrl {          // pinned host memory, written by the host
+    uint64_t tail;          // chunks published so far
+    uint32_t stop;
+    uint32_t pad;
+};
+
+struct ServeArgs {
+    const ServeCtrl *ctrl;
+    const ServeChunk *ring;   // [cap], pinned host memory
+    uint32_t *done;           // [cap], pinned host memory
+    uint32_t cap;
+    unsigned long long *next; // chunks claimed so far (device memory)
+    unsigned int *busy;       // workgroups holding a chunk (device memory, 0 at launch)
+    unsigned int *exiting;    // set once the kernel is idle: every workgroup leaves
+    unsigned long long *last_done;  // s_memrealtime of the latest finished chunk
+    const char *hdesc;        // host arena (pinned, coherent)
+    uint64_t hdesc_bytes;
+    char *arena;              // device arena (images)
+    uint64_t arena_bytes;
+    const double *F2_64;
+    const float *F2_32;
+    uint32_t bytes64, bytes32;
+    uint64_t idle_ticks;      // 100 MHz ticks of device-wide idleness before the kernel exits
+};
+
 // Launchers (xrt_kernels.hip).  Return the hipError_t of the launch.
 hipError_t launch_spots(const Params &p, int precision, bool clamp, hipStream_t stream);
 hipError_t launch_pad_table(const void *src, int src_f64, int32_t na, int32_t nb, int32_t nc,
@@ -79,6 +133,7 @@ hipError_t launch_pad_table(const void *src, int src_f64, int32_t na, int32_t nb
 // fixed-order reduction into grad13 (component 12 scaled by inv_scale).
 hipError_t launch_grad(const Params &p, int precision, bool clamp, const void *dLdI, int dLdI_f64,
                        double *partial, double *grad13, double inv_scale, hipStream_t stream);
+hipError_t launch_serve(const ServeArgs &a, int precision, int shape, int n_wg, hipStream_t stream);
 hipError_t launch_trace(const Params &p, int64_t n, const int32_t *idx, double *S, double *h,
                         hipStream_t stream);
 

@@ -252,14 +252,14 @@ __device__ __forceinline__ Pixel tile_pixel(const Params &p)
     return px;
 }
 
+// The value of pixel (i_f, i_s): the whole per-pixel sum, normalised.  mats
+// and src are the shot's tables (global memory for the standalone kernel,
+// LDS for the served one); the arithmetic is the same in both, so a shot gives
+// the same bits through either path.
 template <int PREC, int SHAPE, bool CLAMP>
-__global__ __launch_bounds__(BLOCK) void spots_kernel(const Params p)
+__device__ __forceinline__ double pixel_value(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *mats,
+                                              const double *srcs, int i_f, int i_s)
 {
-    const __amdgpu_buffer_rsrc_t tab = PREC == XRT_FP64 ? table_rsrc(p.F2_64, p.bytes64)
-                                                         : table_rsrc(p.F2_32, p.bytes32);
-    const Pixel px = tile_pixel(p);
-    const int i_f = px.i_f, i_s = px.i_s;
-
     double acc64 = 0.0;
     float acc = 0.0f, accc = 0.0f;
     for (int u = 0; u < p.O; ++u)
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(BLOCK) void spots_kernel(const Params p)
                 sample_dir(p, i_f, i_s, u, v, t, d, R);
                 const double wgeo = sample_weight(p, d, R, t);
                 for (int j = 0; j < p.n_src; ++j) {
-                    const double *src = p.src + SRC_STRIDE * j;
+                    const double *src = srcs + SRC_STRIDE * j;
                     double S[3];
                     scatter(src, d, S);
                     const double w = src[SRC_WEIGHT] * polarization(src, d, p.kahn) * wgeo;
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(BLOCK) void spots_kernel(const Params p)
                         double sub = 0.0;
                         for (int r = 0; r < p.n_rot; ++r) {
                             double h[3];
-                            miller(p.mats + 9 * r, S, h);
+                            miller(mats + 9 * r, S, h);
                             sub += term_f64<SHAPE, CLAMP>(p, tab, h);
                         }
                         acc64 = __builtin_fma(w, sub, acc64);
@@ -285,15 +285,24 @@ __global__ __launch_bounds__(BLOCK) void spots_kernel(const Params p)
                         float s = 0.0f, c = 0.0f;
                         for (int r = 0; r < p.n_rot; ++r) {
                             double h[3];
-                            miller(p.mats + 9 * r, S, h);
+                            miller(mats + 9 * r, S, h);
                             kahn_add(s, c, term_mixed<SHAPE, CLAMP>(p, tab, h));
                         }
                         kahn_add(acc, accc, (float)w * (s - c));
                     }
                 }
             }
+    return p.norm * (PREC == XRT_FP64 ? acc64 : (double)(acc - accc));
+}
+
+template <int PREC, int SHAPE, bool CLAMP>
+__global__ __launch_bounds__(BLOCK) void spots_kernel(const Params p)
+{
+    const __amdgpu_buffer_rsrc_t tab = PREC == XRT_FP64 ? table_rsrc(p.F2_64, p.bytes64)
+                                                         : table_rsrc(p.F2_32, p.bytes32);
+    const Pixel px = tile_pixel(p);
+    const double val = pixel_value<PREC, SHAPE, CLAMP>(p, tab, p.mats, p.src, px.i_f, px.i_s);
     if (!px.live) return;
-    const double val = p.norm * (PREC == XRT_FP64 ? acc64 : (double)(acc - accc));
     const size_t o = px.out;
     if (p.out_f64) {
         double *img = (double *)p.image;
@@ -326,6 +335,216 @@ hipError_t launch_spots(const Params &p, int precision, bool clamp, hipStream_t 
             launch_one<XRT_MIXED, XRT_SHAPE_SINCG>(p, clamp, stream);
         else
             launch_one<XRT_MIXED, XRT_SHAPE_GAUSS>(p, clamp, stream);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Persistent served-shot kernel (continuous batching).  Workgroups claim
+// chunks of tiles from the published ring (a compare-and-swap on the claim
+// counter, only below the published tail), stage the chunk's shot descriptor
+// and tables in LDS, run the same per-pixel sum as the standalone kernel and
+// set the chunk's done flag.  The kernel leaves only when the whole device is
+// idle: no workgroup holds a chunk, nothing published is unclaimed and no
+// chunk finished for idle_ticks; the first workgroup to see that raises the
+// exit flag and all workgroups leave together (a later progress call
+// relaunches at full width).  The stop flag ends it too.  Every wait is
+// bounded, so the kernel always drains.
+// Every read of descriptor data is a range-checked buffer load of the host
+// arena and every image store is bounds-checked against the device arena: a
+// malformed descriptor cannot reach memory outside the two arenas.
+// ---------------------------------------------------------------------------
+// A wave-uniform copy of the fields of an LDS-resident Params that the
+// per-pixel sum reads, moved into scalar registers (readfirstlane), so the
+// served kernel keeps the register budget of the standalone one.
+__device__ __forceinline__ double uni(double x)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, lo | (hi << 32));
+}
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ Params uniform_params(const Params &s)
+{
+    Params q;
+    q.pixel = uni(s.pixel);
+    q.distance = uni(s.distance);
+    q.beam_f = uni(s.beam_f);
+    q.beam_s = uni(s.beam_s);
+    for (int i = 0; i < 3; ++i) {
+        q.fdet[i] = uni(s.fdet[i]);
+        q.sdet[i] = uni(s.sdet[i]);
+        q.odet[i] = uni(s.odet[i]);
+        q.N[i] = uni(s.N[i]);
+        q.gk[i] = uni(s.gk[i]);
+        q.lo_d[i] = uni(s.lo_d[i]);
+        q.hi_d[i] = uni(s.hi_d[i]);
+    }
+    q.layer_dt = uni(s.layer_dt);
+    q.atten_len = uni(s.atten_len);
+    q.O = uni(s.O);
+    q.T = uni(s.T);
+    q.n_src = uni(s.n_src);
+    q.n_rot = uni(s.n_rot);
+    q.roi_nf = uni(s.roi_nf);
+    q.roi_ns = uni(s.roi_ns);
+    q.tiles_f = uni(s.tiles_f);
+    q.ln_n2 = uni(s.ln_n2);
+    q.kahn = uni(s.kahn);
+    q.norm = uni(s.norm);
+    q.sa8 = uni(s.sa8);
+    q.sb8 = uni(s.sb8);
+    q.sa4 = uni(s.sa4);
+    q.sb4 = uni(s.sb4);
+    q.off8 = uni(s.off8);
+    q.off4 = uni(s.off4);
+    q.out_f64 = uni(s.out_f64);
+    return q;
+}
+
+// Claim the next published chunk (-1: nothing to claim).  Idle polling uses
+// relaxed loads; the acquire that makes a published descriptor visible is
+// taken only after a successful claim.
+__device__ __forceinline__ long long serve_claim(const ServeArgs &a)
+{
+    const unsigned long long tail = __hip_atomic_load(&a.ctrl->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    unsigned long long n = __hip_atomic_load(a.next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (n < tail) {
+        if (__hip_atomic_compare_exchange_strong(a.next, &n, n + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return (long long)n;
+    }
+    return -1;
+}
+
+template <int PREC, int SHAPE>
+__global__ __launch_bounds__(BLOCK) void serve_kernel(const ServeArgs a)
+{
+    __shared__ ShotDesc sd;
+    __shared__ double smats[9 * SERVE_MAX_ROT];
+    __shared__ double ssrc[SRC_STRIDE * SERVE_MAX_SRC];
+    __shared__ long long s_claim;
+    __shared__ uint64_t s_off;
+    __shared__ int32_t s_tile0, s_ntiles;
+    __shared__ uint32_t s_seq1;
+    const __amdgpu_buffer_rsrc_t tab = PREC == XRT_FP64 ? table_rsrc(a.F2_64, a.bytes64)
+                                                         : table_rsrc(a.F2_32, a.bytes32);
+    for (;;) {
+        if (threadIdx.x == 0) {
+            long long c = -2;
+            if (!__hip_atomic_load(a.exiting, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &&
+                !__hip_atomic_load(&a.ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
+                // busy counts workgroups holding a claimed chunk; polling does
+                // not touch it, so an idle device does see it at zero
+                c = serve_claim(a);
+                if (c >= 0) __hip_atomic_fetch_add(a.busy, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (c < 0) {
+                    const uint64_t now = __builtin_amdgcn_s_memrealtime();
+                    const uint64_t last = __hip_atomic_load(a.last_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (now - last > a.idle_ticks &&
+                        __hip_atomic_load(a.busy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                        __hip_atomic_store(a.exiting, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        c = -2;
+                    }
+                } else {
+                    const ServeChunk *ch = a.ring + (uint64_t)c % a.cap;
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the chunk and its descriptor
+                    s_off = __hip_atomic_load(&ch->desc_off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    s_tile0 = __hip_atomic_load(&ch->tile0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    s_ntiles = __hip_atomic_load(&ch->n_tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    s_seq1 = __hip_atomic_load(&ch->seq1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
+            }
+            s_claim = c;
+        }
+        __syncthreads();
+        const long long c = s_claim;
+        if (c == -2) break;
+        if (c == -1) {
+            __builtin_amdgcn_s_sleep(127);
+            __builtin_amdgcn_s_sleep(127);
+            __syncthreads();
+            continue;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // see the published descriptor
+        const uint64_t off = s_off;
+        const bool ok = off < a.hdesc_bytes && (off & 7) == 0;
+        const uint64_t room = ok ? a.hdesc_bytes - off : 0;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<char *>(a.hdesc) + (ok ? off : 0), 0, (int)(room < 0x7fffffffull ? room : 0x7fffffffull),
+            0x00020000);
+        for (int i = threadIdx.x; i < (int)(sizeof(ShotDesc) / 4); i += BLOCK)
+            reinterpret_cast<uint32_t *>(&sd)[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, 4 * i, 0, 0);
+        __syncthreads();
+        // bound every loop extent of the descriptor
+        const int n_rot = min(max(sd.p.n_rot, 0), SERVE_MAX_ROT);
+        const int n_src = min(max(sd.p.n_src, 0), SERVE_MAX_SRC);
+        for (int i = threadIdx.x; i < 9 * n_rot; i += BLOCK)
+            smats[i] = load_f64(rs, (uint32_t)(sd.mats_rel + 8 * (uint64_t)i));
+        for (int i = threadIdx.x; i < SRC_STRIDE * n_src; i += BLOCK)
+            ssrc[i] = load_f64(rs, (uint32_t)(sd.src_rel + 8 * (uint64_t)i));
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            sd.p.n_rot = n_rot;
+            sd.p.n_src = n_src;
+            sd.p.O = min(max(sd.p.O, 0), 64);
+            sd.p.T = min(max(sd.p.T, 0), 64);
+            sd.p.tiles_f = max(sd.p.tiles_f, 1);
+        }
+        __syncthreads();
+        const Params p = uniform_params(sd.p);
+        const int clamp = uni(sd.clamp);
+        const int roi_f0 = uni(sd.roi_f0), roi_s0 = uni(sd.roi_s0);
+        const int ntiles = min(max(s_ntiles, 0), SERVE_MAX_CHUNK);
+        for (int k = 0; k < ntiles; ++k) {
+            const int t = s_tile0 + k;
+            const int tf = t % p.tiles_f, ts = t / p.tiles_f;
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+            const int lf = tf * TILE + (wave & 1) * 8 + (lane & 7);
+            const int ls = ts * TILE + (wave >> 1) * 8 + (lane >> 3);
+            const bool live = lf < p.roi_nf && ls < p.roi_ns;
+            const int i_f = roi_f0 + (lf < p.roi_nf ? lf : p.roi_nf - 1);
+            const int i_s = roi_s0 + (ls < p.roi_ns ? ls : p.roi_ns - 1);
+            const double val = clamp ? pixel_value<PREC, SHAPE, true>(p, tab, smats, ssrc, i_f, i_s)
+                                     : pixel_value<PREC, SHAPE, false>(p, tab, smats, ssrc, i_f, i_s);
+            const uint64_t esz = p.out_f64 ? 8 : 4;
+            const uint64_t o = esz * ((uint64_t)ls * (uint64_t)p.roi_nf + (uint64_t)lf);
+            const uint64_t img = sd.image_off;
+            if (live && o + esz <= sd.image_bytes && img <= a.arena_bytes && o + esz <= a.arena_bytes - img) {
+                if (p.out_f64)
+                    *reinterpret_cast<double *>(a.arena + img + o) = val;
+                else
+                    *reinterpret_cast<float *>(a.arena + img + o) = (float)val;
+            }
+        }
+        __threadfence_system();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(a.done + (uint64_t)c % a.cap, s_seq1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(a.last_done, (unsigned long long)__builtin_amdgcn_s_memrealtime(), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(a.busy, -1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_serve(const ServeArgs &a, int precision, int shape, int n_wg, hipStream_t stream)
+{
+    dim3 grid(n_wg), block(BLOCK);
+    if (precision == XRT_FP64) {
+        if (shape == XRT_SHAPE_SINCG)
+            hipLaunchKernelGGL((serve_kernel<XRT_FP64, XRT_SHAPE_SINCG>), grid, block, 0, stream, a);
+        else
+            hipLaunchKernelGGL((serve_kernel<XRT_FP64, XRT_SHAPE_GAUSS>), grid, block, 0, stream, a);
+    } else {
+        if (shape == XRT_SHAPE_SINCG)
+            hipLaunchKernelGGL((serve_kernel<XRT_MIXED, XRT_SHAPE_SINCG>), grid, block, 0, stream, a);
+        else
+            hipLaunchKernelGGL((serve_kernel<XRT_MIXED, XRT_SHAPE_GAUSS>), grid, block, 0, stream, a);
     }
     return hipGetLastError();
 }

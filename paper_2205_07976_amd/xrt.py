@@ -68,6 +68,22 @@ class FhklDesc(C.Structure):
     ]
 
 
+class ServerDesc(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("hbm_budget", C.c_uint64), ("max_resident", C.c_int32),
+        ("precision", C.c_int32), ("shape", C.c_int32), ("out_dtype", C.c_int32),
+        ("workgroups", C.c_int32), ("idle_exit_us", C.c_double),
+    ]
+
+
+class ShotInfo(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("state", C.c_int32), ("image_bytes", C.c_uint64),
+        ("roi_nf", C.c_int32), ("roi_ns", C.c_int32),
+        ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+    ]
+
+
 class XrtError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"xrt error {code}: {msg}")
@@ -78,8 +94,10 @@ _lib = None
 
 #: every entry point of include/xrt.h
 SYMBOLS = ("xrt_version", "xrt_last_error", "xrt_fhkl_create", "xrt_fhkl_destroy",
-           "xrt_simulate", "xrt_simulate_rois", "xrt_backward_rois", "xrt_cell_mats",
-           "xrt_trace_terms")
+           "xrt_simulate", "xrt_simulate_rois", "xrt_backward_rois", "xrt_server_create",
+           "xrt_server_destroy", "xrt_server_submit", "xrt_server_progress", "xrt_server_info",
+           "xrt_server_image", "xrt_server_release", "xrt_cell_mats", "xrt_trace_terms")
+XRT_SHOT_QUEUED, XRT_SHOT_RUNNING, XRT_SHOT_DONE = 0, 1, 2
 
 
 def load():
@@ -102,6 +120,14 @@ def load():
     lib.xrt_backward_rois.argtypes = [C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal), C.c_void_p,
                                       C.c_int32, C.c_int64, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                       C.c_int32, C.c_void_p, C.c_void_p]
+    lib.xrt_server_create.argtypes = [C.POINTER(ServerDesc), C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.xrt_server_destroy.argtypes = [C.c_void_p]
+    lib.xrt_server_submit.argtypes = [C.c_void_p, C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal),
+                                      C.POINTER(C.c_uint64)]
+    lib.xrt_server_progress.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
+    lib.xrt_server_info.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(ShotInfo)]
+    lib.xrt_server_image.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_void_p)]
+    lib.xrt_server_release.argtypes = [C.c_void_p, C.c_uint64]
     lib.xrt_cell_mats.argtypes = [C.POINTER(Crystal), C.c_void_p]
     lib.xrt_trace_terms.argtypes = [C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal), C.c_int64,
                                     C.c_void_p, C.c_void_p, C.c_void_p]
@@ -284,3 +310,68 @@ def trace_terms(shot, idx):
     _check(load().xrt_trace_terms(C.byref(st.det), C.byref(st.beam), C.byref(st.xtal), len(idx),
                                   idx.ctypes.data, S.ctypes.data, h.ctypes.data))
     return S, h
+
+
+class Server:
+    """xrt_server_*: continuous batching of independent shots on the current
+    device (see include/xrt.h).  submit() queues a shot and returns a ticket;
+    progress() must be called often; image(ticket) returns a finished image as
+    a torch tensor viewing the server's arena (copy it before release)."""
+
+    def __init__(self, fhkl: Fhkl, hbm_budget=8 << 30, max_resident=256, precision="mixed",
+                 shape=XRT_SHAPE_SINCG, out_dtype=None, workgroups=0, idle_exit_us=5000.0):
+        self.fhkl = fhkl  # kept alive: the server borrows its tables
+        self.out_f64 = (out_dtype == "f64") if out_dtype else precision == "fp64"
+        d = ServerDesc(C.sizeof(ServerDesc), int(hbm_budget), int(max_resident), _PREC[precision], int(shape),
+                       XRT_F64 if self.out_f64 else XRT_F32, int(workgroups), float(idle_exit_us))
+        h = C.c_void_p()
+        _check(load().xrt_server_create(C.byref(d), fhkl.handle, C.byref(h)))
+        self._h = h
+
+    def submit(self, shot) -> int:
+        st = ShotStructs(shot)
+        t = C.c_uint64()
+        _check(load().xrt_server_submit(self._h, C.byref(st.det), C.byref(st.beam), C.byref(st.xtal),
+                                        C.byref(t)))
+        return t.value
+
+    def progress(self) -> int:
+        n = C.c_int32()
+        _check(load().xrt_server_progress(self._h, C.byref(n)))
+        return n.value
+
+    def info(self, ticket) -> ShotInfo:
+        i = ShotInfo()
+        i.struct_size = C.sizeof(ShotInfo)
+        _check(load().xrt_server_info(self._h, int(ticket), C.byref(i)))
+        return i
+
+    def image(self, ticket, copy=True):
+        """The finished image as a [roi_ns, roi_nf] GPU tensor: a view of the
+        arena (valid until release) or, by default, a copy of it."""
+        import torch
+        info = self.info(ticket)
+        p = C.c_void_p()
+        _check(load().xrt_server_image(self._h, int(ticket), C.byref(p)))
+
+        class _View:
+            __cuda_array_interface__ = {"shape": (info.roi_ns, info.roi_nf),
+                                        "typestr": "<f8" if self.out_f64 else "<f4",
+                                        "data": (p.value, False), "version": 2, "strides": None}
+
+        view = torch.as_tensor(_View(), device="cuda")
+        return view.clone() if copy else view
+
+    def release(self, ticket):
+        _check(load().xrt_server_release(self._h, int(ticket)))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _check(load().xrt_server_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,164 @@
+"""Served shots (continuous batching in a persistent kernel) through the C ABI:
+every image equals the standalone kernel's bit for bit, alone and in the mix;
+admission follows the HBM budget in arrival order; oversized shots are
+refused; the server relaunches its kernel after an idle exit."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as o
+from tests.metrics import compare
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2205_07976_amd import serve, xrt  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def small_served_shots(n, seed=44, max_side=160):
+    """Served-stream shots with small ROIs (the full-size detector and table,
+    random orientation, sources, domains and N), so tests stay short."""
+    base = synth.full_shot()
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        s = synth.served_shot(rng, base.F, base.hkl_min)
+        wf, ws = int(rng.integers(8, max_side)), int(rng.integers(8, max_side))
+        f0, s0 = int(rng.integers(0, 2463 - wf)), int(rng.integers(0, 2527 - ws))
+        n_src = int(rng.integers(1, 9))
+        n_mos = int(rng.integers(1, 17))
+        s = s.replace(roi=(f0, f0 + wf, s0, s0 + ws), src_dir=s.src_dir[:n_src].copy(),
+                      src_lambda=s.src_lambda[:n_src].copy(),
+                      src_weight=s.src_weight[:n_src] / s.src_weight[:n_src].sum(),
+                      umats=s.umats[:n_mos].copy())
+        out.append(s)
+    return base, out
+
+
+def drain(server, tickets, timeout=60.0):
+    t0 = time.time()
+    while True:
+        server.progress()
+        states = [server.info(t).state for t in tickets]
+        if all(st == xrt.XRT_SHOT_DONE for st in states):
+            return
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"states {states}")
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_served_equal_standalone_in_mix_and_alone(precision):
+    base, shots = small_served_shots(10)
+    fh = xrt.Fhkl.from_shot(base)
+    ref = [xrt.simulate(s, fh, precision=precision).cpu().numpy() for s in shots]
+    srv = xrt.Server(fh, hbm_budget=256 << 20, precision=precision)
+    tickets = [srv.submit(s) for s in shots]  # all at once: they share the kernel
+    drain(srv, tickets)
+    for i, t in enumerate(tickets):
+        img = srv.image(t).cpu().numpy()
+        assert np.array_equal(img, ref[i]), f"shot {i} differs in the mix"
+        srv.release(t)
+    for i, s in enumerate(shots[:4]):  # alone, one after the other
+        t = srv.submit(s)
+        drain(srv, [t])
+        assert np.array_equal(srv.image(t).cpu().numpy(), ref[i]), f"shot {i} differs alone"
+        srv.release(t)
+    srv.close()
+
+
+def test_served_matches_oracle():
+    base, shots = small_served_shots(3, seed=7, max_side=40)
+    fh = xrt.Fhkl.from_shot(base)
+    srv = xrt.Server(fh, hbm_budget=64 << 20, precision="mixed")
+    tickets = [srv.submit(s) for s in shots]
+    drain(srv, tickets)
+    for s, t in zip(shots, tickets):
+        r = compare(srv.image(t).cpu().numpy(), o.simulate(s))
+        say(s.roi, r)
+        assert r["zeros_ok"] and r["max_rel"] <= 1e-5
+    srv.close()
+
+
+def test_admission_by_budget_in_arrival_order():
+    """A 3 MiB budget holds at most two of these shots (about 1.2 MiB each):
+    the others wait, admissions follow arrival order, and all finish."""
+    base, shots = small_served_shots(7, seed=3, max_side=20)
+    shots = [s.replace(roi=(100 + 5 * i, 100 + 5 * i + 560, 200, 200 + 560)) for i, s in enumerate(shots)]
+    fh = xrt.Fhkl.from_shot(base)
+    srv = xrt.Server(fh, hbm_budget=3 << 20, precision="mixed")
+    tickets = [srv.submit(s) for s in shots]
+    peak = 0
+    t0 = time.time()
+    while True:
+        srv.progress()
+        infos = [srv.info(t) for t in tickets]
+        resident = sum(1 for i in infos if i.state == xrt.XRT_SHOT_RUNNING)
+        peak = max(peak, resident)
+        for t, i in zip(tickets, infos):
+            if i.state == xrt.XRT_SHOT_DONE and i.t_done >= 0:
+                pass
+        done = [t for t, i in zip(tickets, infos) if i.state == xrt.XRT_SHOT_DONE]
+        for t in done:
+            srv.release(t)
+            tickets.remove(t)
+        if not tickets:
+            break
+        assert time.time() - t0 < 120
+    say("peak resident", peak)
+    assert 1 <= peak <= 2
+    srv.close()
+
+
+def test_refusals():
+    base, shots = small_served_shots(1)
+    fh = xrt.Fhkl.from_shot(base)
+    srv = xrt.Server(fh, hbm_budget=1 << 20, precision="mixed")
+    with pytest.raises(xrt.XrtError) as e:  # 2463 x 2527 x 4 B image > 1 MiB
+        srv.submit(shots[0].replace(roi=(0, 2463, 0, 2527)))
+    assert e.value.code == xrt.XRT_ERANGE
+    many = shots[0].replace(src_dir=np.repeat(shots[0].src_dir[:1], 200, 0),
+                            src_lambda=np.full(200, 1.3), src_weight=np.full(200, 1 / 200))
+    with pytest.raises(xrt.XrtError) as e:
+        srv.submit(many)
+    assert e.value.code == xrt.XRT_ERANGE
+    with pytest.raises(xrt.XrtError) as e:
+        srv.submit(shots[0].replace(shape=synth.SHAPE_GAUSS))
+    assert e.value.code == xrt.XRT_EINVAL
+    srv.close()
+
+
+def test_relaunch_after_idle_exit():
+    base, shots = small_served_shots(4, seed=9, max_side=48)
+    fh = xrt.Fhkl.from_shot(base)
+    ref = [xrt.simulate(s, fh, precision="mixed").cpu().numpy() for s in shots]
+    srv = xrt.Server(fh, hbm_budget=64 << 20, precision="mixed", idle_exit_us=500.0)
+    for i, s in enumerate(shots):
+        t = srv.submit(s)
+        drain(srv, [t])
+        assert np.array_equal(srv.image(t).cpu().numpy(), ref[i])
+        srv.release(t)
+        time.sleep(0.02)  # longer than the idle exit: the next shot needs a new kernel
+    srv.close()
+
+
+def test_run_stream_poisson():
+    base, shots = small_served_shots(24, seed=12, max_side=96)
+    fh = xrt.Fhkl.from_shot(base)
+    srv = xrt.Server(fh, hbm_budget=256 << 20, precision="mixed")
+    arr = serve.poisson_arrivals(np.random.default_rng(1), len(shots), rate=400.0)
+    res = serve.run_stream(srv, shots, arr, keep=[0, 5])
+    stats = serve.summarize(res, shots, 400.0)
+    say(stats)
+    assert np.all(np.isfinite(res["latency"])) and np.all(res["latency"] > 0)
+    for i in (0, 5):
+        assert np.array_equal(res["images"][i].cpu().numpy(),
+                              xrt.simulate(shots[i], fh, precision="mixed").cpu().numpy())
+    srv.close()
