@@ -88,15 +88,14 @@ struct ShotDesc {
     uint64_t image_off;     // byte offset of the image in the device arena
     uint64_t image_bytes;
     int32_t roi_f0, roi_s0;
-    int32_t clamp;
-    int32_t pad;
 };
 
 struct ServeChunk {         // written by the host before the tail publishes it
     uint64_t desc_off;      // byte offset of the ShotDesc in the host arena
     int32_t tile0, n_tiles;
     uint32_t seq1;          // chunk number + 1: the value its done flag takes
-    uint32_t pad;
+    uint32_t shot;          // the shot's serial number (nonzero): with desc_off it
+                            // names the descriptor a workgroup may keep in LDS
 };
 
 struct ServeCtrl {          // pinned host memory, written by the host
@@ -125,6 +124,9 @@ struct ServeArgs {
 };
 
 // Launchers (xrt_kernels.hip).  Return the hipError_t of the launch.
+// serve_blocks_per_cu: workgroups of the persistent kernel one compute unit
+// holds at once (0 on error).
+int serve_blocks_per_cu(int precision, int shape);
 hipError_t launch_spots(const Params &p, int precision, bool clamp, hipStream_t stream);
 hipError_t launch_pad_table(const void *src, int src_f64, int32_t na, int32_t nb, int32_t nc,
                             int32_t pad, double F_default, double *F2_64, float *F2_32,

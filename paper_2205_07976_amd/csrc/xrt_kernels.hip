@@ -343,16 +343,19 @@ hipError_t launch_spots(const Params &p, int precision, bool clamp, hipStream_t 
 // Persistent served-shot kernel (continuous batching).  Workgroups claim
 // chunks of tiles from the published ring (a compare-and-swap on the claim
 // counter, only below the published tail), stage the chunk's shot descriptor
-// and tables in LDS, run the same per-pixel sum as the standalone kernel and
-// set the chunk's done flag.  The kernel leaves only when the whole device is
-// idle: no workgroup holds a chunk, nothing published is unclaimed and no
-// chunk finished for idle_ticks; the first workgroup to see that raises the
-// exit flag and all workgroups leave together (a later progress call
-// relaunches at full width).  The stop flag ends it too.  Every wait is
-// bounded, so the kernel always drains.
-// Every read of descriptor data is a range-checked buffer load of the host
-// arena and every image store is bounds-checked against the device arena: a
-// malformed descriptor cannot reach memory outside the two arenas.
+// and tables in LDS (kept there while the next chunk belongs to the same shot),
+// run the same per-pixel sum as the standalone kernel and set the chunk's done
+// flag.  Served shots always take the clamped table index: it gives the same
+// bits as the clamp-free one whenever the latter is valid, and one variant
+// keeps the kernel within 128 VGPRs (4 waves per SIMD).  The kernel leaves
+// only when the whole device is idle: no workgroup holds a chunk, nothing
+// published is unclaimed and no chunk finished for idle_ticks; the first
+// workgroup to see that raises the exit flag and all workgroups leave together
+// (a later progress call relaunches at full width).  The stop flag ends it once
+// nothing published is left.  Every wait is bounded, so the kernel always
+// drains.  Every read of descriptor data is a range-checked buffer load of the
+// host arena and every image store is bounds-checked against the device arena:
+// a malformed descriptor cannot reach memory outside the two arenas.
 // ---------------------------------------------------------------------------
 // A wave-uniform copy of the fields of an LDS-resident Params that the
 // per-pixel sum reads, moved into scalar registers (readfirstlane), so the
@@ -421,27 +424,41 @@ __device__ __forceinline__ long long serve_claim(const ServeArgs &a)
 }
 
 template <int PREC, int SHAPE>
-__global__ __launch_bounds__(BLOCK) void serve_kernel(const ServeArgs a)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void serve_kernel(const ServeArgs a)
 {
     __shared__ ShotDesc sd;
     __shared__ double smats[9 * SERVE_MAX_ROT];
     __shared__ double ssrc[SRC_STRIDE * SERVE_MAX_SRC];
     __shared__ long long s_claim;
-    __shared__ uint64_t s_off;
+    __shared__ uint64_t s_off, s_have_off;
     __shared__ int32_t s_tile0, s_ntiles;
-    __shared__ uint32_t s_seq1;
+    __shared__ uint32_t s_seq1, s_shot, s_have_shot;  // s_have_*: the descriptor now in LDS
     const __amdgpu_buffer_rsrc_t tab = PREC == XRT_FP64 ? table_rsrc(a.F2_64, a.bytes64)
                                                          : table_rsrc(a.F2_32, a.bytes32);
+    if (threadIdx.x == 0) {
+        s_have_off = ~0ull;
+        s_have_shot = 0;
+    }
+    int backoff = 1;  // idle polling interval, in units of s_sleep(127)
     for (;;) {
         if (threadIdx.x == 0) {
             long long c = -2;
-            if (!__hip_atomic_load(a.exiting, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &&
-                !__hip_atomic_load(&a.ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
+            if (!__hip_atomic_load(a.exiting, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                 // busy counts workgroups holding a claimed chunk; polling does
                 // not touch it, so an idle device does see it at zero
                 c = serve_claim(a);
-                if (c >= 0) __hip_atomic_fetch_add(a.busy, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (c < 0) {
+                if (c >= 0) {
+                    __hip_atomic_fetch_add(a.busy, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const ServeChunk *ch = a.ring + (uint64_t)c % a.cap;
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the chunk and its descriptor
+                    s_off = __hip_atomic_load(&ch->desc_off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    s_tile0 = __hip_atomic_load(&ch->tile0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    s_ntiles = __hip_atomic_load(&ch->n_tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    s_seq1 = __hip_atomic_load(&ch->seq1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    s_shot = __hip_atomic_load(&ch->shot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                } else if (__hip_atomic_load(&a.ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
+                    c = -2;  // stop is honoured once nothing published is left
+                } else {
                     const uint64_t now = __builtin_amdgcn_s_memrealtime();
                     const uint64_t last = __hip_atomic_load(a.last_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (now - last > a.idle_ticks &&
@@ -449,13 +466,6 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(const ServeArgs a)
                         __hip_atomic_store(a.exiting, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         c = -2;
                     }
-                } else {
-                    const ServeChunk *ch = a.ring + (uint64_t)c % a.cap;
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the chunk and its descriptor
-                    s_off = __hip_atomic_load(&ch->desc_off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                    s_tile0 = __hip_atomic_load(&ch->tile0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                    s_ntiles = __hip_atomic_load(&ch->n_tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                    s_seq1 = __hip_atomic_load(&ch->seq1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 }
             }
             s_claim = c;
@@ -464,39 +474,47 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(const ServeArgs a)
         const long long c = s_claim;
         if (c == -2) break;
         if (c == -1) {
-            __builtin_amdgcn_s_sleep(127);
-            __builtin_amdgcn_s_sleep(127);
+            // idle: poll the host-memory tail at a falling rate (about 3.4 us
+            // per unit, at most 16 units), so idle workgroups do not crowd the
+            // host link that busy ones read their chunks through
+            for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(127);
+            backoff = backoff < 16 ? 2 * backoff : 16;
             __syncthreads();
             continue;
         }
+        backoff = 1;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // see the published descriptor
         const uint64_t off = s_off;
-        const bool ok = off < a.hdesc_bytes && (off & 7) == 0;
-        const uint64_t room = ok ? a.hdesc_bytes - off : 0;
-        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<char *>(a.hdesc) + (ok ? off : 0), 0, (int)(room < 0x7fffffffull ? room : 0x7fffffffull),
-            0x00020000);
-        for (int i = threadIdx.x; i < (int)(sizeof(ShotDesc) / 4); i += BLOCK)
-            reinterpret_cast<uint32_t *>(&sd)[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, 4 * i, 0, 0);
-        __syncthreads();
-        // bound every loop extent of the descriptor
-        const int n_rot = min(max(sd.p.n_rot, 0), SERVE_MAX_ROT);
-        const int n_src = min(max(sd.p.n_src, 0), SERVE_MAX_SRC);
-        for (int i = threadIdx.x; i < 9 * n_rot; i += BLOCK)
-            smats[i] = load_f64(rs, (uint32_t)(sd.mats_rel + 8 * (uint64_t)i));
-        for (int i = threadIdx.x; i < SRC_STRIDE * n_src; i += BLOCK)
-            ssrc[i] = load_f64(rs, (uint32_t)(sd.src_rel + 8 * (uint64_t)i));
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            sd.p.n_rot = n_rot;
-            sd.p.n_src = n_src;
-            sd.p.O = min(max(sd.p.O, 0), 64);
-            sd.p.T = min(max(sd.p.T, 0), 64);
-            sd.p.tiles_f = max(sd.p.tiles_f, 1);
+        if (off != s_have_off || s_shot != s_have_shot) {
+            // a new shot for this workgroup: stage its descriptor and tables
+            const bool ok = off < a.hdesc_bytes && (off & 7) == 0;
+            const uint64_t room = ok ? a.hdesc_bytes - off : 0;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<char *>(a.hdesc) + (ok ? off : 0), 0, (int)(room < 0x7fffffffull ? room : 0x7fffffffull),
+                0x00020000);
+            for (int i = threadIdx.x; i < (int)(sizeof(ShotDesc) / 4); i += BLOCK)
+                reinterpret_cast<uint32_t *>(&sd)[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, 4 * i, 0, 0);
+            __syncthreads();
+            // bound every loop extent of the descriptor
+            const int n_rot = min(max(sd.p.n_rot, 0), SERVE_MAX_ROT);
+            const int n_src = min(max(sd.p.n_src, 0), SERVE_MAX_SRC);
+            for (int i = threadIdx.x; i < 9 * n_rot; i += BLOCK)
+                smats[i] = load_f64(rs, (uint32_t)(sd.mats_rel + 8 * (uint64_t)i));
+            for (int i = threadIdx.x; i < SRC_STRIDE * n_src; i += BLOCK)
+                ssrc[i] = load_f64(rs, (uint32_t)(sd.src_rel + 8 * (uint64_t)i));
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                sd.p.n_rot = n_rot;
+                sd.p.n_src = n_src;
+                sd.p.O = min(max(sd.p.O, 0), 64);
+                sd.p.T = min(max(sd.p.T, 0), 64);
+                sd.p.tiles_f = max(sd.p.tiles_f, 1);
+                s_have_off = off;
+                s_have_shot = s_shot;
+            }
+            __syncthreads();
         }
-        __syncthreads();
         const Params p = uniform_params(sd.p);
-        const int clamp = uni(sd.clamp);
         const int roi_f0 = uni(sd.roi_f0), roi_s0 = uni(sd.roi_s0);
         const int ntiles = min(max(s_ntiles, 0), SERVE_MAX_CHUNK);
         for (int k = 0; k < ntiles; ++k) {
@@ -508,8 +526,7 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(const ServeArgs a)
             const bool live = lf < p.roi_nf && ls < p.roi_ns;
             const int i_f = roi_f0 + (lf < p.roi_nf ? lf : p.roi_nf - 1);
             const int i_s = roi_s0 + (ls < p.roi_ns ? ls : p.roi_ns - 1);
-            const double val = clamp ? pixel_value<PREC, SHAPE, true>(p, tab, smats, ssrc, i_f, i_s)
-                                     : pixel_value<PREC, SHAPE, false>(p, tab, smats, ssrc, i_f, i_s);
+            const double val = pixel_value<PREC, SHAPE, true>(p, tab, smats, ssrc, i_f, i_s);
             const uint64_t esz = p.out_f64 ? 8 : 4;
             const uint64_t o = esz * ((uint64_t)ls * (uint64_t)p.roi_nf + (uint64_t)lf);
             const uint64_t img = sd.image_off;
@@ -530,6 +547,23 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(const ServeArgs a)
         }
         __syncthreads();
     }
+}
+
+static const void *serve_fn(int precision, int shape)
+{
+    if (precision == XRT_FP64)
+        return shape == XRT_SHAPE_SINCG ? (const void *)serve_kernel<XRT_FP64, XRT_SHAPE_SINCG>
+                                        : (const void *)serve_kernel<XRT_FP64, XRT_SHAPE_GAUSS>;
+    return shape == XRT_SHAPE_SINCG ? (const void *)serve_kernel<XRT_MIXED, XRT_SHAPE_SINCG>
+                                    : (const void *)serve_kernel<XRT_MIXED, XRT_SHAPE_GAUSS>;
+}
+
+int serve_blocks_per_cu(int precision, int shape)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, serve_fn(precision, shape), BLOCK, 0) != hipSuccess)
+        return 0;
+    return n;
 }
 
 hipError_t launch_serve(const ServeArgs &a, int precision, int shape, int n_wg, hipStream_t stream)

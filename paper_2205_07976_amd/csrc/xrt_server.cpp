@@ -48,6 +48,8 @@ namespace {
 
 constexpr uint64_t ALIGN = 256;
 constexpr uint32_t RING = 1u << 16;
+constexpr int TILE_PIXELS = 256;           // 16 x 16 pixels per tile
+constexpr uint64_t CHUNK_TERMS = 1u << 20;  // pixel-terms a chunk aims at
 
 uint64_t align_up(uint64_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
@@ -247,7 +249,16 @@ xrt_status admit(xrt_server *s)
         sh.state = XRT_SHOT_RUNNING;
         sh.t_admit = s->now();
         sh.n_tiles = d.p.n_tiles;
-        sh.chunk_tiles = std::max(1, std::min(16, (sh.n_tiles + 2 * s->n_wg - 1) / (2 * s->n_wg)));
+        // chunk size: about CHUNK_TERMS pixel-terms (a few ms of one
+        // workgroup, so a shot admitted later waits at most that long for a
+        // workgroup, and the last chunks of a shot end close together), and
+        // no more tiles than spread the shot over every workgroup
+        const uint64_t per_tile = (uint64_t)TILE_PIXELS * (uint64_t)d.p.O * (uint64_t)d.p.O * (uint64_t)d.p.T *
+                                  (uint64_t)d.p.n_src * (uint64_t)d.p.n_rot;
+        const uint64_t by_cost = std::max<uint64_t>(1, CHUNK_TERMS / std::max<uint64_t>(per_tile, 1));
+        const uint64_t by_spread = ((uint64_t)sh.n_tiles + s->n_wg - 1) / s->n_wg;
+        sh.chunk_tiles = (int32_t)std::max<uint64_t>(
+            1, std::min<uint64_t>({by_cost, by_spread, (uint64_t)xrt::SERVE_MAX_CHUNK}));
         sh.chunks_total = (sh.n_tiles + sh.chunk_tiles - 1) / sh.chunk_tiles;
         s->resident++;
         s->admitted.push_back(sh.ticket);
@@ -256,11 +267,13 @@ xrt_status admit(xrt_server *s)
     return XRT_OK;
 }
 
-// (3) publication: one chunk per admitted shot per round (so small shots are
-// not stuck behind large ones), while the ring has room.
+// (3) publication: one chunk per admitted shot per round, while fewer than
+// two chunks per workgroup are in flight.  The shallow queue keeps a shot
+// admitted later from waiting behind the whole of an earlier large one: its
+// chunks enter the ring as soon as earlier chunks finish.
 void publish(xrt_server *s)
 {
-    const size_t depth = RING - 1;
+    const size_t depth = std::min<size_t>(RING - 1, 2 * (size_t)s->n_wg);
     bool any = false;
     while (s->inflight.size() < depth && !s->admitted.empty()) {
         if (s->rr >= s->admitted.size()) s->rr = 0;
@@ -271,7 +284,7 @@ void publish(xrt_server *s)
         c.tile0 = sh.next_tile;
         c.n_tiles = std::min(sh.chunk_tiles, sh.n_tiles - sh.next_tile);
         c.seq1 = (uint32_t)(seq + 1);
-        c.pad = 0;
+        c.shot = (uint32_t)sh.ticket ? (uint32_t)sh.ticket : 1u;
         sh.next_tile += c.n_tiles;
         s->inflight.push_back({seq, sh.ticket});
         s->tail++;
@@ -333,9 +346,11 @@ xrt_status xrt_server_create(const xrt_server_desc *desc, const xrt_fhkl *fhkl, 
     hipError_t e = hipGetDevice(&s->device);
     int cus = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
-    // two persistent workgroups per compute unit leave a slot free on every
-    // unit for other kernels (result copies, the caller's own work)
-    s->n_wg = desc->workgroups ? desc->workgroups : 2 * std::max(cus, 1);
+    // one workgroup per compute unit fewer than it holds leaves a slot free on
+    // every unit for other kernels (result copies, the caller's own work)
+    const int per_cu = e == hipSuccess ? xrt::serve_blocks_per_cu(desc->precision, desc->shape) : 0;
+    if (e == hipSuccess && per_cu < 1) e = hipErrorInvalidConfiguration;
+    s->n_wg = desc->workgroups ? desc->workgroups : std::max(per_cu - 1, 1) * std::max(cus, 1);
     s->host_bytes = (uint64_t)std::min(desc->max_resident, 4096) * (32u << 10);
     if (e == hipSuccess) e = hipMalloc((void **)&s->dev_arena, desc->hbm_budget);
     if (e == hipSuccess) e = hipMalloc((void **)&s->dev_ctl, 4 * sizeof(unsigned long long));
