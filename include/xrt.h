@@ -237,9 +237,9 @@ typedef struct xrt_server_desc {
     int32_t precision;      /* XRT_FP64 or XRT_MIXED */
     int32_t shape;          /* XRT_SHAPE_* of every served shot */
     int32_t out_dtype;      /* XRT_F32 or XRT_F64 images */
-    int32_t workgroups;     /* persistent workgroups, in [0, 65536]; 0 = one
-                               fewer per compute unit than it holds at once,
-                               which leaves room on every unit for other work */
+    int32_t workgroups;     /* persistent workgroups, in [0, 65536]; 0 = as
+                               many as the device holds at once less eight,
+                               which leaves room for small kernels beside it */
     double idle_exit_us;    /* once no workgroup has work and no chunk has
                                finished for this long, the kernel exits, in
                                [1, 1e6] us; the next progress call relaunches */

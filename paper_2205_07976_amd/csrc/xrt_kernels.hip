@@ -252,11 +252,33 @@ __device__ __forceinline__ Pixel tile_pixel(const Params &p)
     return px;
 }
 
+// Fractional Miller indices of term r.  Without PF the matrix is read where
+// it is used (scalar loads for the standalone kernel); with PF, m holds
+// matrix r and is replaced by matrix r + 1, whose reads are issued before h.
+template <bool PF>
+__device__ __forceinline__ void hkl(const Params &p, const double *mats, double m[9], int r, const double S[3],
+                                    double h[3])
+{
+    if (PF) {
+        double mn[9];
+        const double *nx = mats + 9 * (r + 1 < p.n_rot ? r + 1 : r);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) mn[q] = nx[q];
+        miller(m, S, h);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) m[q] = mn[q];
+    } else {
+        miller(mats + 9 * r, S, h);
+    }
+}
+
 // The value of pixel (i_f, i_s): the whole per-pixel sum, normalised.  mats
 // and src are the shot's tables (global memory for the standalone kernel,
 // LDS for the served one); the arithmetic is the same in both, so a shot gives
-// the same bits through either path.
-template <int PREC, int SHAPE, bool CLAMP>
+// the same bits through either path.  PF (tables in LDS): the next spindle x
+// domain matrix is read while the current term is evaluated, so the LDS
+// latency is hidden behind one term instead of stalling every term.
+template <int PREC, int SHAPE, bool CLAMP, bool PF = false>
 __device__ __forceinline__ double pixel_value(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *mats,
                                               const double *srcs, int i_f, int i_s)
 {
@@ -273,11 +295,16 @@ __device__ __forceinline__ double pixel_value(const Params &p, __amdgpu_buffer_r
                     double S[3];
                     scatter(src, d, S);
                     const double w = src[SRC_WEIGHT] * polarization(src, d, p.kahn) * wgeo;
+                    double m[9];  // PF: the matrix of the current term
+                    if (PF) {
+#pragma unroll
+                        for (int q = 0; q < 9; ++q) m[q] = mats[q];
+                    }
                     if (PREC == XRT_FP64) {
                         double sub = 0.0;
                         for (int r = 0; r < p.n_rot; ++r) {
                             double h[3];
-                            miller(mats + 9 * r, S, h);
+                            hkl<PF>(p, mats, m, r, S, h);
                             sub += term_f64<SHAPE, CLAMP>(p, tab, h);
                         }
                         acc64 = __builtin_fma(w, sub, acc64);
@@ -285,7 +312,7 @@ __device__ __forceinline__ double pixel_value(const Params &p, __amdgpu_buffer_r
                         float s = 0.0f, c = 0.0f;
                         for (int r = 0; r < p.n_rot; ++r) {
                             double h[3];
-                            miller(mats + 9 * r, S, h);
+                            hkl<PF>(p, mats, m, r, S, h);
                             kahn_add(s, c, term_mixed<SHAPE, CLAMP>(p, tab, h));
                         }
                         kahn_add(acc, accc, (float)w * (s - c));
@@ -347,7 +374,8 @@ hipError_t launch_spots(const Params &p, int precision, bool clamp, hipStream_t 
 // run the same per-pixel sum as the standalone kernel and set the chunk's done
 // flag.  Served shots always take the clamped table index: it gives the same
 // bits as the clamp-free one whenever the latter is valid, and one variant
-// keeps the kernel within 128 VGPRs (4 waves per SIMD).  The kernel leaves
+// keeps the kernel within 168 VGPRs (3 waves per SIMD) with the next matrix's
+// LDS reads in flight during each term.  The kernel leaves
 // only when the whole device is idle: no workgroup holds a chunk, nothing
 // published is unclaimed and no chunk finished for idle_ticks; the first
 // workgroup to see that raises the exit flag and all workgroups leave together
@@ -424,7 +452,7 @@ __device__ __forceinline__ long long serve_claim(const ServeArgs &a)
 }
 
 template <int PREC, int SHAPE>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void serve_kernel(const ServeArgs a)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void serve_kernel(const ServeArgs a)
 {
     __shared__ ShotDesc sd;
     __shared__ double smats[9 * SERVE_MAX_ROT];
@@ -439,7 +467,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         s_have_off = ~0ull;
         s_have_shot = 0;
     }
-    int backoff = 1;  // idle polling interval, in units of s_sleep(127)
+    // idle polling interval, in units of s_sleep(127) (about 3.4 us): one
+    // workgroup per XCD (the first eight) polls at most every 16 units, the
+    // others at most every 256, so new work is seen within tens of us while
+    // idle workgroups stay off the memory paths the busy ones use
+    const int max_backoff = blockIdx.x < 8 ? 16 : 256;
+    int backoff = 1;
     for (;;) {
         if (threadIdx.x == 0) {
             long long c = -2;
@@ -474,11 +507,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         const long long c = s_claim;
         if (c == -2) break;
         if (c == -1) {
-            // idle: poll the host-memory tail at a falling rate (about 3.4 us
-            // per unit, at most 16 units), so idle workgroups do not crowd the
-            // host link that busy ones read their chunks through
+            // idle: poll again at a falling rate
             for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(127);
-            backoff = backoff < 16 ? 2 * backoff : 16;
+            backoff = backoff < max_backoff ? 2 * backoff : max_backoff;
             __syncthreads();
             continue;
         }
@@ -526,7 +557,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
             const bool live = lf < p.roi_nf && ls < p.roi_ns;
             const int i_f = roi_f0 + (lf < p.roi_nf ? lf : p.roi_nf - 1);
             const int i_s = roi_s0 + (ls < p.roi_ns ? ls : p.roi_ns - 1);
-            const double val = pixel_value<PREC, SHAPE, true>(p, tab, smats, ssrc, i_f, i_s);
+            const double val = pixel_value<PREC, SHAPE, true, true>(p, tab, smats, ssrc, i_f, i_s);
             const uint64_t esz = p.out_f64 ? 8 : 4;
             const uint64_t o = esz * ((uint64_t)ls * (uint64_t)p.roi_nf + (uint64_t)lf);
             const uint64_t img = sd.image_off;

@@ -346,11 +346,11 @@ xrt_status xrt_server_create(const xrt_server_desc *desc, const xrt_fhkl *fhkl, 
     hipError_t e = hipGetDevice(&s->device);
     int cus = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
-    // one workgroup per compute unit fewer than it holds leaves a slot free on
-    // every unit for other kernels (result copies, the caller's own work)
+    // as many workgroups as the device holds at once, less eight: the free
+    // slots let small kernels (result copies) run beside the persistent one
     const int per_cu = e == hipSuccess ? xrt::serve_blocks_per_cu(desc->precision, desc->shape) : 0;
     if (e == hipSuccess && per_cu < 1) e = hipErrorInvalidConfiguration;
-    s->n_wg = desc->workgroups ? desc->workgroups : std::max(per_cu - 1, 1) * std::max(cus, 1);
+    s->n_wg = desc->workgroups ? desc->workgroups : std::max(per_cu * std::max(cus, 1) - 8, 1);
     s->host_bytes = (uint64_t)std::min(desc->max_resident, 4096) * (32u << 10);
     if (e == hipSuccess) e = hipMalloc((void **)&s->dev_arena, desc->hbm_budget);
     if (e == hipSuccess) e = hipMalloc((void **)&s->dev_ctl, 4 * sizeof(unsigned long long));
