@@ -77,9 +77,9 @@ def cpu_baseline(shot, budget_s=15.0):
         t0 = time.perf_counter()
         o.simulate(shot, pix, nthreads=cores)
         dt = time.perf_counter() - t0
-        if dt >= budget_s / 4 or n >= 65536:
+        if dt >= 0.6 * budget_s or n >= 262144:
             break
-        n = min(65536, int(n * max(2.0, budget_s / max(dt, 1e-3) / 2)))
+        n = min(262144, max(2 * n, int(n * budget_s / max(dt, 1e-3))))
     terms = n * shot.terms_per_pixel
     return {"value": terms / dt / 1e9, "unit": "Gterm/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} seeded pixels of the full-size shot ({terms:.3e} terms, {dt:.1f} s)"}
