@@ -288,6 +288,15 @@ xrt_status xrt_server_image(xrt_server *srv, uint64_t ticket, const void **dev_i
 /* Free a finished shot's memory and slot.  EBUSY if not done. */
 xrt_status xrt_server_release(xrt_server *srv, uint64_t ticket);
 
+/* Diagnostics: the kernels' sin(pi x) for |x| <= 1/2 (the reduced arguments f
+ * and g of the lattice factor, section II's crystal-size transform), exactly
+ * as the binary64 kernel (dev_s64) and the mixed kernel (dev_s32, from
+ * (float)x) form it: x * P(x^2) with P a relative-minimax polynomial.
+ * dev_x: [n] binary64; outputs [n]; either output may be NULL, not both.
+ * Enqueued on `stream`; outside [-1/2, 1/2] the value is the polynomial's.
+ * Errors: ERANGE (n < 0), EINVAL (NULL arrays), EDEVICE. */
+xrt_status xrt_sinpi(const double *dev_x, int64_t n, double *dev_s64, float *dev_s32, hipStream_t stream);
+
 /* Diagnostics: the library's lab-frame cell matrices M_{k,m} (host output,
  * [n_phi*n_mos][3][3], rows a', b', c'), exactly as the kernels receive them. */
 xrt_status xrt_cell_mats(const xrt_crystal *xtal, double *host_out);

@@ -136,6 +136,7 @@ hipError_t launch_pad_table(const void *src, int src_f64, int32_t na, int32_t nb
 hipError_t launch_grad(const Params &p, int precision, bool clamp, const void *dLdI, int dLdI_f64,
                        double *partial, double *grad13, double inv_scale, hipStream_t stream);
 hipError_t launch_serve(const ServeArgs &a, int precision, int shape, int n_wg, hipStream_t stream);
+hipError_t launch_sinpi(const double *x, int64_t n, double *s64, float *s32, hipStream_t stream);
 hipError_t launch_trace(const Params &p, int64_t n, const int32_t *idx, double *S, double *h,
                         hipStream_t stream);
 

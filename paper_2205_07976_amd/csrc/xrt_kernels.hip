@@ -158,8 +158,8 @@ __device__ __forceinline__ double term_f64(const Params &p, __amdgpu_buffer_rsrc
             const double fa = __builtin_fmax(__builtin_fabs(h[i] - hr[i]), F_FLOOR);
             const double t = p.N[i] * fa;
             const double g = t - __builtin_rint(t);
-            num *= g * sinpi_over_x(g * g);
-            den *= fa * sinpi_over_x(fa * fa);
+            num *= sinpi_reduced(g);
+            den *= sinpi_reduced(fa);
         }
         const double q = div_newton(num, den);
         L2 = q * q;
@@ -192,8 +192,8 @@ __device__ __forceinline__ float term_mixed(const Params &p, __amdgpu_buffer_rsr
             const double t = p.N[i] * fa;
             const float g = (float)(t - __builtin_rint(t));
             const float f = (float)fa;
-            num *= g * sinpi_over_x(g * g);
-            den *= f * sinpi_over_x(f * f);
+            num *= sinpi_reduced(g);
+            den *= sinpi_reduced(f);
         }
         const float q = num * __builtin_amdgcn_rcpf(den);
         L2 = q * q;
@@ -830,6 +830,21 @@ __global__ void trace_kernel(const Params p, int64_t n, const int32_t *idx, doub
         S_out[3 * q + i] = S[i];
         h_out[3 * q + i] = h[i];
     }
+}
+
+__global__ void sinpi_kernel(const double *x, int64_t n, double *s64, float *s32)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    if (s64) s64[q] = sinpi_reduced(x[q]);
+    if (s32) s32[q] = sinpi_reduced((float)x[q]);
+}
+
+hipError_t launch_sinpi(const double *x, int64_t n, double *s64, float *s32, hipStream_t stream)
+{
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(sinpi_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, x, n, s64, s32);
+    return hipGetLastError();
 }
 
 hipError_t launch_trace(const Params &p, int64_t n, const int32_t *idx, double *S, double *h,

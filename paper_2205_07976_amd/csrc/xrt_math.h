@@ -35,4 +35,8 @@ __device__ __forceinline__ float sinpi_over_x(float y)
     return p;
 }
 
+// sin(pi x) for |x| <= 1/2, composed as the lattice factor uses it.
+__device__ __forceinline__ double sinpi_reduced(double x) { return x * sinpi_over_x(x * x); }
+__device__ __forceinline__ float sinpi_reduced(float x) { return x * sinpi_over_x(x * x); }
+
 }  // namespace xrt

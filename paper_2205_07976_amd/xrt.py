@@ -96,7 +96,7 @@ _lib = None
 SYMBOLS = ("xrt_version", "xrt_last_error", "xrt_fhkl_create", "xrt_fhkl_destroy",
            "xrt_simulate", "xrt_simulate_rois", "xrt_backward_rois", "xrt_server_create",
            "xrt_server_destroy", "xrt_server_submit", "xrt_server_progress", "xrt_server_info",
-           "xrt_server_image", "xrt_server_release", "xrt_cell_mats", "xrt_trace_terms")
+           "xrt_server_image", "xrt_server_release", "xrt_cell_mats", "xrt_trace_terms", "xrt_sinpi")
 XRT_SHOT_QUEUED, XRT_SHOT_RUNNING, XRT_SHOT_DONE = 0, 1, 2
 
 
@@ -131,6 +131,7 @@ def load():
     lib.xrt_cell_mats.argtypes = [C.POINTER(Crystal), C.c_void_p]
     lib.xrt_trace_terms.argtypes = [C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal), C.c_int64,
                                     C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.xrt_sinpi.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
     for name in SYMBOLS:
         if name != "xrt_last_error":
             getattr(lib, name).restype = C.c_int32
@@ -310,6 +311,20 @@ def trace_terms(shot, idx):
     _check(load().xrt_trace_terms(C.byref(st.det), C.byref(st.beam), C.byref(st.xtal), len(idx),
                                   idx.ctypes.data, S.ctypes.data, h.ctypes.data))
     return S, h
+
+
+def sinpi(x, stream=None):
+    """The kernels' sin(pi x) (|x| <= 1/2) of a binary64 CUDA tensor: returns
+    (binary64 form, binary32 form of (float)x)."""
+    import torch
+    if not (x.is_cuda and x.dtype == torch.float64):
+        raise ValueError("x must be a binary64 tensor on the GPU")
+    x = x.contiguous()
+    s64 = torch.empty_like(x)
+    s32 = torch.empty(x.shape, dtype=torch.float32, device=x.device)
+    _check(load().xrt_sinpi(C.c_void_p(x.data_ptr()), x.numel(), C.c_void_p(s64.data_ptr()),
+                            C.c_void_p(s32.data_ptr()), _stream(stream)))
+    return s64, s32
 
 
 class Server:

@@ -129,3 +129,11 @@ def test_trace_index_validation():
     with pytest.raises(xrt.XrtError) as e:
         xrt.trace_terms(shot, np.array([[0, 0, 4, 0, 0, 0]], np.int32))  # sub >= O^2
     assert e.value.code == xrt.XRT_ERANGE
+
+
+def test_sinpi_validation():
+    lib = xrt.load()
+    assert lib.xrt_sinpi(C.c_void_p(8), -1, C.c_void_p(8), None, None) == xrt.XRT_ERANGE
+    assert lib.xrt_sinpi(None, 4, C.c_void_p(8), None, None) == xrt.XRT_EINVAL
+    assert lib.xrt_sinpi(C.c_void_p(8), 4, None, None, None) == xrt.XRT_EINVAL
+    assert lib.xrt_sinpi(None, 0, None, None, None) == xrt.XRT_OK  # nothing to do, nothing launched
