@@ -168,7 +168,13 @@ xrt_status xrt_fhkl_destroy(xrt_fhkl *fhkl);
  *              in out_dtype (the separate add-image kernel of section III,
  *              fused into the store).
  * The call uploads a few small tables (cell matrices, sources) stream-ordered
- * and launches one kernel on `stream`.
+ * and launches one kernel on `stream` (two for split sums, below).
+ * Summation order: when the region has fewer than 2048 tiles of 16 x 16
+ * pixels, each pixel's loop over (sub-pixel, layer, source) is cut into K
+ * contiguous parts summed by different workgroups and the K part sums are
+ * added in part order.  K is a function of the shot alone (tile count and
+ * loop extents), so a shot's image does not depend on where or beside what it
+ * runs.
  * Errors: EINVAL / ERANGE on any malformed field, ENOMEM, EDEVICE. */
 xrt_status xrt_simulate(const xrt_detector *det, const xrt_beam *beam,
                         const xrt_crystal *xtal, const xrt_fhkl *fhkl,
@@ -183,6 +189,7 @@ xrt_status xrt_simulate(const xrt_detector *det, const xrt_beam *beam,
  *                fields are ignored).  Read during the call.
  *  dev_images    device pointer, [n_roi][roi_ns][roi_nf] of out_dtype,
  *                overwritten.
+ * Summation order as xrt_simulate, with the tile count of all regions.
  * Errors: as xrt_simulate; ERANGE for n_roi outside [1, 2^22]. */
 xrt_status xrt_simulate_rois(const xrt_detector *det, const xrt_beam *beam,
                              const xrt_crystal *xtal, const xrt_fhkl *fhkl,

@@ -424,6 +424,23 @@ struct Plan {
     bool clamp = true;
 };
 
+// Split factor of the per-pixel sums: a region list of fewer than
+// SPLIT_TARGET tiles has each pixel's outer iterations (sub-pixel, layer,
+// source) cut into K parts so that about SPLIT_TARGET workgroups share the
+// work, each part keeping at least SPLIT_MIN_TERMS terms per pixel.  K
+// depends on the shot alone (tile count and loop extents), never on the
+// device or on other work, so a shot's bits are the same in every path.
+constexpr int64_t SPLIT_TARGET = 2048;
+constexpr int64_t SPLIT_MIN_TERMS = 1024;
+
+int32_t split_factor(int64_t n_tiles, int64_t n_outer, int64_t terms_per_pixel)
+{
+    if (n_tiles >= SPLIT_TARGET) return 1;
+    int64_t k = (SPLIT_TARGET + n_tiles - 1) / n_tiles;
+    k = std::min<int64_t>({k, n_outer, terms_per_pixel / SPLIT_MIN_TERMS, (int64_t)xrt::SERVE_MAX_SPLIT});
+    return (int32_t)std::max<int64_t>(k, 1);
+}
+
 xrt_status make_plan(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal,
                      const xrt_fhkl *fhkl, int64_t n_roi, const int32_t *origins, int32_t roi_nf,
                      int32_t roi_ns, bool with_q, Plan &pl)
@@ -483,6 +500,9 @@ xrt_status make_plan(const xrt_detector *det, const xrt_beam *beam, const xrt_cr
     p.off8 = biased_zero_offset(fhkl, 8);
     p.off4 = biased_zero_offset(fhkl, 4);
     pl.clamp = !h_inside(det, box, beam, pl.host.data(), pl.n_rot, fhkl);
+    const int64_t n_outer = (int64_t)p.O * p.O * p.T * p.n_src;
+    p.split = split_factor(p.n_tiles, n_outer, n_outer * p.n_rot);
+    p.partial = nullptr;
     return XRT_OK;
 }
 
@@ -511,10 +531,13 @@ xrt_status run_spots(Plan &pl, int32_t precision, void *dev_image, int32_t out_d
     pl.p.accumulate = accumulate;
     double *tables = nullptr;
     const size_t bytes = sizeof(double) * pl.host.size();
-    HIP_TRY(hipMallocAsync((void **)&tables, bytes, s), "hipMallocAsync");
+    // split sums: partial sums [tile][part][lane] after the tables
+    const size_t part_bytes = pl.p.split > 1 ? sizeof(double) * (size_t)pl.p.n_tiles * pl.p.split * 256 : 0;
+    HIP_TRY(hipMallocAsync((void **)&tables, bytes + part_bytes, s), "hipMallocAsync");
     hipError_t e = hipMemcpyAsync(tables, pl.host.data(), bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
         bind_tables(pl, tables);
+        pl.p.partial = part_bytes ? tables + pl.host.size() : nullptr;
         e = xrt::launch_spots(pl.p, precision, pl.clamp, s);
     }
     hipError_t e2 = hipFreeAsync(tables, s);
@@ -550,6 +573,14 @@ xrt_status served_descriptor(const xrt_detector *det, const xrt_beam *beam, cons
     d->roi_s0 = det->roi_s0;
     tables.assign(pl.host.begin(), pl.host.begin() + (ptrdiff_t)pl.o_orig);
     return XRT_OK;
+}
+
+int32_t split_of(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal)
+{
+    const int64_t nf = det->roi_f1 - det->roi_f0, ns = det->roi_s1 - det->roi_s0;
+    const int64_t n_tiles = ((nf + 15) / 16) * ((ns + 15) / 16);
+    const int64_t n_outer = (int64_t)det->oversample * det->oversample * det->n_layers * beam->n_src;
+    return split_factor(n_tiles, n_outer, n_outer * xtal->n_phi * xtal->n_mos);
 }
 
 void fhkl_tables(const xrt_fhkl *t, const double **F2_64, const float **F2_32, uint32_t *bytes64, uint32_t *bytes32)
@@ -607,6 +638,7 @@ xrt_status xrt_backward_rois(const xrt_detector *det, const xrt_beam *beam, cons
         return fail(XRT_EINVAL, "the adjoint is defined for the Gaussian shape only");
     Plan pl;
     if ((st = make_plan(det, beam, xtal, fhkl, n_roi, host_origins, roi_nf, roi_ns, true, pl))) return st;
+    pl.p.split = 1;  // the adjoint reduces per workgroup; its sums are never split
     if (xtal->scale == 0.0) return fail(XRT_EINVAL, "scale must be nonzero for its gradient");
     for (int i = 0; i < 9; ++i) pl.p.m0[i] = 0.0;
     for (int i = 0; i < 3; ++i) {

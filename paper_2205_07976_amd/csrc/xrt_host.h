@@ -23,6 +23,10 @@ xrt_status check_shot(const xrt_detector *det, const xrt_beam *beam, const xrt_c
 xrt_status served_descriptor(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal,
                              const xrt_fhkl *fhkl, int32_t out_dtype, ShotDesc *d, std::vector<double> &tables);
 
+// Split factor of a validated one-ROI shot's per-pixel sums (the rule
+// xrt_simulate applies; 1 = whole sums).
+int32_t split_of(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal);
+
 // Device tables of a structure-factor handle.
 void fhkl_tables(const xrt_fhkl *t, const double **F2_64, const float **F2_32, uint32_t *bytes64,
                  uint32_t *bytes32);

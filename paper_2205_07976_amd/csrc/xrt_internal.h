@@ -68,6 +68,12 @@ struct Params {
     void *image;
     int32_t out_f64;
     int32_t accumulate;
+    // split sums: each pixel's outer iterations (sub-pixel, layer, source) in
+    // `split` contiguous parts, one workgroup per (tile, part); part sums go
+    // to partial[tile][part][lane] and are added in part order afterwards.
+    // split == 1: whole sums, no partials.
+    int32_t split;
+    double *partial;
 };
 
 // ---------------------------------------------------------------------------
@@ -79,7 +85,9 @@ struct Params {
 // ---------------------------------------------------------------------------
 constexpr int SERVE_MAX_ROT = 256;   // spindle steps x mosaic domains per served shot
 constexpr int SERVE_MAX_SRC = 128;   // sources per served shot
-constexpr int SERVE_MAX_CHUNK = 64;  // tiles per chunk
+constexpr int SERVE_MAX_CHUNK = 64;  // tiles (or tile parts) per chunk
+constexpr int SERVE_MAX_SPLIT = 64;  // parts per pixel sum
+enum { CHUNK_COMPUTE = 0, CHUNK_REDUCE = 1 };
 
 struct ShotDesc {
     Params p;               // pointer fields unused
@@ -87,6 +95,8 @@ struct ShotDesc {
     uint64_t src_rel;
     uint64_t image_off;     // byte offset of the image in the device arena
     uint64_t image_bytes;
+    uint64_t partial_off;   // byte offset of the partial sums in the device arena
+    uint64_t partial_bytes; // (split > 1 only)
     int32_t roi_f0, roi_s0;
 };
 
@@ -96,6 +106,9 @@ struct ServeChunk {         // written by the host before the tail publishes it
     uint32_t seq1;          // chunk number + 1: the value its done flag takes
     uint32_t shot;          // the shot's serial number (nonzero): with desc_off it
                             // names the descriptor a workgroup may keep in LDS
+    int32_t kind;           // CHUNK_COMPUTE: units tile * split + part;
+                            // CHUNK_REDUCE: tiles whose parts are all done
+    int32_t pad;
 };
 
 struct ServeCtrl {          // pinned host memory, written by the host

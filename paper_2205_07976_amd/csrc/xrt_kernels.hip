@@ -236,9 +236,8 @@ struct Pixel {
     size_t out;  // element index in the [n_roi][roi_ns][roi_nf] output
 };
 
-__device__ __forceinline__ Pixel tile_pixel(const Params &p)
+__device__ __forceinline__ Pixel tile_pixel(const Params &p, int tile)
 {
-    const int tile = xcd_tile(blockIdx.x, p.n_tiles);
     const int roi = tile / p.tiles_per_roi, t = tile - roi * p.tiles_per_roi;
     const int tf = t % p.tiles_f, ts = t / p.tiles_f;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -272,65 +271,69 @@ __device__ __forceinline__ void hkl(const Params &p, const double *mats, double 
     }
 }
 
-// The value of pixel (i_f, i_s): the whole per-pixel sum, normalised.  mats
-// and src are the shot's tables (global memory for the standalone kernel,
-// LDS for the served one); the arithmetic is the same in both, so a shot gives
-// the same bits through either path.  PF (tables in LDS): the next spindle x
-// domain matrix is read while the current term is evaluated, so the LDS
-// latency is hidden behind one term instead of stalling every term.
+// The per-pixel sum of pixel (i_f, i_s), not normalised, over the part
+// [q0, q1) of its outer iterations q = ((u O + v) T + t) n_src + j (sub-pixel
+// (u, v), layer t, source j), each summing all spindle x domain terms.  The
+// whole range [0, O^2 T n_src) runs the loops in the order of the plain sum.
+// mats and src are the shot's tables (global memory for the standalone
+// kernel, LDS for the served one); the arithmetic is the same in both, so a
+// shot gives the same bits through either path.  PF (tables in LDS): the next
+// spindle x domain matrix is read while the current term is evaluated, so the
+// LDS latency is hidden behind one term instead of stalling every term.
 template <int PREC, int SHAPE, bool CLAMP, bool PF = false>
-__device__ __forceinline__ double pixel_value(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *mats,
-                                              const double *srcs, int i_f, int i_s)
+__device__ __forceinline__ double pixel_sum(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *mats,
+                                            const double *srcs, int i_f, int i_s, int q0, int q1)
 {
     double acc64 = 0.0;
     float acc = 0.0f, accc = 0.0f;
-    for (int u = 0; u < p.O; ++u)
-        for (int v = 0; v < p.O; ++v)
-            for (int t = 0; t < p.T; ++t) {
-                double d[3], R;
-                sample_dir(p, i_f, i_s, u, v, t, d, R);
-                const double wgeo = sample_weight(p, d, R, t);
-                for (int j = 0; j < p.n_src; ++j) {
-                    const double *src = srcs + SRC_STRIDE * j;
-                    double S[3];
-                    scatter(src, d, S);
-                    const double w = src[SRC_WEIGHT] * polarization(src, d, p.kahn) * wgeo;
-                    double m[9];  // PF: the matrix of the current term
-                    if (PF) {
+    const int per_t = p.T, per_v = p.O * p.T;
+    int uvt = q0 / p.n_src, j0 = q0 - uvt * p.n_src;
+    for (int q = q0; q < q1; ++uvt) {
+        const int u = uvt / per_v, v = (uvt - u * per_v) / per_t, t = uvt - u * per_v - v * per_t;
+        double d[3], R;
+        sample_dir(p, i_f, i_s, u, v, t, d, R);
+        const double wgeo = sample_weight(p, d, R, t);
+        const int j1 = min(p.n_src, j0 + (q1 - q));
+        for (int j = j0; j < j1; ++j) {
+            const double *src = srcs + SRC_STRIDE * j;
+            double S[3];
+            scatter(src, d, S);
+            const double w = src[SRC_WEIGHT] * polarization(src, d, p.kahn) * wgeo;
+            double m[9];  // PF: the matrix of the current term
+            if (PF) {
 #pragma unroll
-                        for (int q = 0; q < 9; ++q) m[q] = mats[q];
-                    }
-                    if (PREC == XRT_FP64) {
-                        double sub = 0.0;
-                        for (int r = 0; r < p.n_rot; ++r) {
-                            double h[3];
-                            hkl<PF>(p, mats, m, r, S, h);
-                            sub += term_f64<SHAPE, CLAMP>(p, tab, h);
-                        }
-                        acc64 = __builtin_fma(w, sub, acc64);
-                    } else {
-                        float s = 0.0f, c = 0.0f;
-                        for (int r = 0; r < p.n_rot; ++r) {
-                            double h[3];
-                            hkl<PF>(p, mats, m, r, S, h);
-                            kahn_add(s, c, term_mixed<SHAPE, CLAMP>(p, tab, h));
-                        }
-                        kahn_add(acc, accc, (float)w * (s - c));
-                    }
-                }
+                for (int c = 0; c < 9; ++c) m[c] = mats[c];
             }
-    return p.norm * (PREC == XRT_FP64 ? acc64 : (double)(acc - accc));
+            if (PREC == XRT_FP64) {
+                double sub = 0.0;
+                for (int r = 0; r < p.n_rot; ++r) {
+                    double h[3];
+                    hkl<PF>(p, mats, m, r, S, h);
+                    sub += term_f64<SHAPE, CLAMP>(p, tab, h);
+                }
+                acc64 = __builtin_fma(w, sub, acc64);
+            } else {
+                float s = 0.0f, c = 0.0f;
+                for (int r = 0; r < p.n_rot; ++r) {
+                    double h[3];
+                    hkl<PF>(p, mats, m, r, S, h);
+                    kahn_add(s, c, term_mixed<SHAPE, CLAMP>(p, tab, h));
+                }
+                kahn_add(acc, accc, (float)w * (s - c));
+            }
+        }
+        q += j1 - j0;
+        j0 = 0;
+    }
+    return PREC == XRT_FP64 ? acc64 : (double)(acc - accc);
 }
 
-template <int PREC, int SHAPE, bool CLAMP>
-__global__ __launch_bounds__(BLOCK) void spots_kernel(const Params p)
+// Part k of K of the outer iterations: [k n / K, (k + 1) n / K).
+__device__ __forceinline__ int part_begin(int k, int K, int n) { return (int)((int64_t)k * n / K); }
+
+// The stored value of a pixel and its store (with the accumulate option).
+__device__ __forceinline__ void store_pixel(const Params &p, size_t o, double val)
 {
-    const __amdgpu_buffer_rsrc_t tab = PREC == XRT_FP64 ? table_rsrc(p.F2_64, p.bytes64)
-                                                         : table_rsrc(p.F2_32, p.bytes32);
-    const Pixel px = tile_pixel(p);
-    const double val = pixel_value<PREC, SHAPE, CLAMP>(p, tab, p.mats, p.src, px.i_f, px.i_s);
-    if (!px.live) return;
-    const size_t o = px.out;
     if (p.out_f64) {
         double *img = (double *)p.image;
         img[o] = p.accumulate ? img[o] + val : val;
@@ -340,14 +343,55 @@ __global__ __launch_bounds__(BLOCK) void spots_kernel(const Params p)
     }
 }
 
+// Sum of the K partial sums of one pixel, in part order.
+__device__ __forceinline__ double sum_parts(const double *part, int K)
+{
+    double s = part[0];
+    for (int k = 1; k < K; ++k) s += part[(size_t)k * BLOCK];
+    return s;
+}
+
+// One workgroup per (tile, part): with p.split == 1 the whole sum of every
+// pixel of a 16 x 16 tile, stored; with p.split = K > 1, part k of each sum,
+// written to p.partial[tile][k][lane] for reduce_kernel.
+template <int PREC, int SHAPE, bool CLAMP>
+__global__ __launch_bounds__(BLOCK) void spots_kernel(const Params p)
+{
+    const __amdgpu_buffer_rsrc_t tab = PREC == XRT_FP64 ? table_rsrc(p.F2_64, p.bytes64)
+                                                         : table_rsrc(p.F2_32, p.bytes32);
+    const int unit = xcd_tile(blockIdx.x, p.n_tiles * p.split);
+    const int tile = unit / p.split, k = unit - tile * p.split;
+    const Pixel px = tile_pixel(p, tile);
+    const int n_outer = p.O * p.O * p.T * p.n_src;
+    const double sum = pixel_sum<PREC, SHAPE, CLAMP>(p, tab, p.mats, p.src, px.i_f, px.i_s,
+                                                     part_begin(k, p.split, n_outer),
+                                                     part_begin(k + 1, p.split, n_outer));
+    if (p.split > 1) {
+        p.partial[((size_t)tile * p.split + k) * BLOCK + threadIdx.x] = sum;
+        return;
+    }
+    if (px.live) store_pixel(p, px.out, p.norm * sum);
+}
+
+// Split sums: each pixel's K partial sums added in part order, normalised,
+// stored.
+__global__ __launch_bounds__(BLOCK) void reduce_kernel(const Params p)
+{
+    const int tile = blockIdx.x;
+    const Pixel px = tile_pixel(p, tile);
+    const double sum = sum_parts(p.partial + (size_t)tile * p.split * BLOCK + threadIdx.x, p.split);
+    if (px.live) store_pixel(p, px.out, p.norm * sum);
+}
+
 template <int PREC, int SHAPE>
 static void launch_one(const Params &p, bool clamp, hipStream_t stream)
 {
-    dim3 grid(p.n_tiles), block(BLOCK);
+    dim3 grid(p.n_tiles * p.split), block(BLOCK);
     if (clamp)
         hipLaunchKernelGGL((spots_kernel<PREC, SHAPE, true>), grid, block, 0, stream, p);
     else
         hipLaunchKernelGGL((spots_kernel<PREC, SHAPE, false>), grid, block, 0, stream, p);
+    if (p.split > 1) hipLaunchKernelGGL(reduce_kernel, dim3(p.n_tiles), block, 0, stream, p);
 }
 
 hipError_t launch_spots(const Params &p, int precision, bool clamp, hipStream_t stream)
@@ -433,6 +477,7 @@ __device__ __forceinline__ Params uniform_params(const Params &s)
     q.off8 = uni(s.off8);
     q.off4 = uni(s.off4);
     q.out_f64 = uni(s.out_f64);
+    q.split = uni(s.split);
     return q;
 }
 
@@ -459,7 +504,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     __shared__ double ssrc[SRC_STRIDE * SERVE_MAX_SRC];
     __shared__ long long s_claim;
     __shared__ uint64_t s_off, s_have_off;
-    __shared__ int32_t s_tile0, s_ntiles;
+    __shared__ int32_t s_tile0, s_ntiles, s_kind;
     __shared__ uint32_t s_seq1, s_shot, s_have_shot;  // s_have_*: the descriptor now in LDS
     const __amdgpu_buffer_rsrc_t tab = PREC == XRT_FP64 ? table_rsrc(a.F2_64, a.bytes64)
                                                          : table_rsrc(a.F2_32, a.bytes32);
@@ -489,6 +534,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
                     s_ntiles = __hip_atomic_load(&ch->n_tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     s_seq1 = __hip_atomic_load(&ch->seq1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     s_shot = __hip_atomic_load(&ch->shot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    s_kind = __hip_atomic_load(&ch->kind, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 } else if (__hip_atomic_load(&a.ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
                     c = -2;  // stop is honoured once nothing published is left
                 } else {
@@ -540,6 +586,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
                 sd.p.O = min(max(sd.p.O, 0), 64);
                 sd.p.T = min(max(sd.p.T, 0), 64);
                 sd.p.tiles_f = max(sd.p.tiles_f, 1);
+                sd.p.split = min(max(sd.p.split, 1), SERVE_MAX_SPLIT);
                 s_have_off = off;
                 s_have_shot = s_shot;
             }
@@ -547,20 +594,40 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
         }
         const Params p = uniform_params(sd.p);
         const int roi_f0 = uni(sd.roi_f0), roi_s0 = uni(sd.roi_s0);
-        const int ntiles = min(max(s_ntiles, 0), SERVE_MAX_CHUNK);
-        for (int k = 0; k < ntiles; ++k) {
-            const int t = s_tile0 + k;
+        const int n_units = min(max(s_ntiles, 0), SERVE_MAX_CHUNK);
+        const int split = p.split;
+        const int n_outer = p.O * p.O * p.T * p.n_src;
+        const uint64_t img = sd.image_off, part = sd.partial_off;
+        for (int i = 0; i < n_units; ++i) {
+            // compute chunk: unit = tile * split + part; reduce chunk: unit = tile
+            const int unit = s_tile0 + i;
+            const int t = s_kind == CHUNK_COMPUTE ? unit / split : unit;
+            const int k = s_kind == CHUNK_COMPUTE ? unit - t * split : 0;
             const int tf = t % p.tiles_f, ts = t / p.tiles_f;
             const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
             const int lf = tf * TILE + (wave & 1) * 8 + (lane & 7);
             const int ls = ts * TILE + (wave >> 1) * 8 + (lane >> 3);
             const bool live = lf < p.roi_nf && ls < p.roi_ns;
-            const int i_f = roi_f0 + (lf < p.roi_nf ? lf : p.roi_nf - 1);
-            const int i_s = roi_s0 + (ls < p.roi_ns ? ls : p.roi_ns - 1);
-            const double val = pixel_value<PREC, SHAPE, true, true>(p, tab, smats, ssrc, i_f, i_s);
+            // partial sums of this tile and lane: [tile][part][lane] binary64
+            const uint64_t pq = part + 8 * (((uint64_t)t * split) * BLOCK + threadIdx.x);
+            const bool parts_ok = part <= a.arena_bytes && pq + 8 * ((uint64_t)(split - 1) * BLOCK + 1) <= a.arena_bytes &&
+                                  8 * (((uint64_t)t * split + split) * BLOCK) <= sd.partial_bytes;
+            double sum;
+            if (s_kind == CHUNK_COMPUTE) {
+                const int i_f = roi_f0 + (lf < p.roi_nf ? lf : p.roi_nf - 1);
+                const int i_s = roi_s0 + (ls < p.roi_ns ? ls : p.roi_ns - 1);
+                sum = pixel_sum<PREC, SHAPE, true, true>(p, tab, smats, ssrc, i_f, i_s, part_begin(k, split, n_outer),
+                                                         part_begin(k + 1, split, n_outer));
+                if (split > 1) {
+                    if (parts_ok) *reinterpret_cast<double *>(a.arena + pq + 8 * (uint64_t)k * BLOCK) = sum;
+                    continue;
+                }
+            } else {
+                sum = parts_ok ? sum_parts(reinterpret_cast<const double *>(a.arena + pq), split) : 0.0;
+            }
+            const double val = p.norm * sum;
             const uint64_t esz = p.out_f64 ? 8 : 4;
             const uint64_t o = esz * ((uint64_t)ls * (uint64_t)p.roi_nf + (uint64_t)lf);
-            const uint64_t img = sd.image_off;
             if (live && o + esz <= sd.image_bytes && img <= a.arena_bytes && o + esz <= a.arena_bytes - img) {
                 if (p.out_f64)
                     *reinterpret_cast<double *>(a.arena + img + o) = val;
@@ -707,7 +774,7 @@ __global__ __launch_bounds__(BLOCK) void grad_kernel(const Params p, const void 
     __shared__ double lds[4];
     const __amdgpu_buffer_rsrc_t tab = PREC == XRT_FP64 ? table_rsrc(p.F2_64, p.bytes64)
                                                          : table_rsrc(p.F2_32, p.bytes32);
-    const Pixel px = tile_pixel(p);
+    const Pixel px = tile_pixel(p, xcd_tile(blockIdx.x, p.n_tiles));
     double gp = 0.0;
     if (px.live) gp = dLdI_f64 ? ((const double *)dLdI)[px.out] : (double)((const float *)dLdI)[px.out];
     double acc[13];

@@ -11,7 +11,7 @@
 //             (2) admit queued shots: first-fit allocation of the image in
 //                 the device arena and of descriptor + tables in a pinned
 //                 host arena, written in place;
-//             (3) publish chunks of every admitted shot round-robin up to a
+//             (3) publish chunks of the admitted shots, least work first, up to a
 //                 bounded depth, then move the tail (release);
 //             (4) launch the persistent kernel if none is running and
 //                 published chunks wait.
@@ -98,10 +98,16 @@ struct Shot {
     xrt_beam beam{};
     xrt_crystal xtal{};
     std::vector<double> dir, lam, weight, umats;
-    uint64_t desc_bytes = 0, image_bytes = 0, footprint = 0;
+    uint64_t desc_bytes = 0, image_bytes = 0, part_bytes = 0, footprint = 0;
     uint64_t desc_off = 0, image_off = 0;  // in the host and device arenas
-    int32_t n_tiles = 0, chunk_tiles = 1, next_tile = 0;
+    int32_t n_tiles = 0, split = 1;
+    uint64_t terms_per_pixel = 0;
+    // the current phase: CHUNK_COMPUTE over units tile * split + part, then,
+    // for split sums, CHUNK_REDUCE over tiles once every part is done
+    int32_t phase = xrt::CHUNK_COMPUTE;
+    int32_t n_units = 0, chunk_units = 1, next_unit = 0;
     int64_t chunks_total = 0, chunks_done = 0;
+    double work_published = 0;  // pixel-terms of the chunks published so far
     double t_submit = 0, t_admit = -1, t_done = -1;
 };
 
@@ -136,8 +142,8 @@ struct xrt_server {
     std::deque<uint64_t> queue;                    // submitted, not admitted (FIFO)
     std::vector<uint64_t> admitted;                // admitted with tiles left to publish
     std::vector<InFlight> inflight;                // published chunks not yet done
+    double vtime = 0;                              // published work of the shot served last
     std::unordered_map<uint64_t, Shot> shots;
-    size_t rr = 0;                                 // round-robin cursor over `admitted`
     std::chrono::steady_clock::time_point t0;
 
     double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
@@ -191,7 +197,29 @@ bool kernel_running(xrt_server *s, hipError_t *err)
     return false;
 }
 
-// (1) done flags -> finished chunks -> finished shots.
+// Chunking of a shot's current phase.  Compute chunks hold about
+// CHUNK_TERMS pixel-terms (a few ms of one workgroup, so a shot admitted later
+// waits at most that long for a workgroup, and the last chunks of a shot end
+// close together) and no more units than spread the phase over every
+// workgroup; reduce chunks (K loads per pixel) are spread the same way.
+void start_phase(xrt_server *s, Shot &sh, int32_t phase)
+{
+    sh.phase = phase;
+    sh.n_units = phase == xrt::CHUNK_COMPUTE ? sh.n_tiles * sh.split : sh.n_tiles;
+    const uint64_t by_spread = ((uint64_t)sh.n_units + s->n_wg - 1) / s->n_wg;
+    uint64_t by_cost = (uint64_t)xrt::SERVE_MAX_CHUNK;
+    if (phase == xrt::CHUNK_COMPUTE) {
+        const uint64_t per_unit = std::max<uint64_t>(1, TILE_PIXELS * sh.terms_per_pixel / (uint64_t)sh.split);
+        by_cost = std::max<uint64_t>(1, CHUNK_TERMS / per_unit);
+    }
+    sh.chunk_units = (int32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>({by_cost, by_spread, (uint64_t)xrt::SERVE_MAX_CHUNK}));
+    sh.next_unit = 0;
+    sh.chunks_total = (sh.n_units + sh.chunk_units - 1) / sh.chunk_units;
+    sh.chunks_done = 0;
+}
+
+// (1) done flags -> finished chunks -> finished phases and shots.
 void collect(xrt_server *s, int32_t *n_done)
 {
     size_t w = 0;
@@ -201,9 +229,14 @@ void collect(xrt_server *s, int32_t *n_done)
         if (flag == (uint32_t)(f.seq + 1)) {
             Shot &sh = s->shots[f.ticket];
             if (++sh.chunks_done == sh.chunks_total) {
-                sh.state = XRT_SHOT_DONE;
-                sh.t_done = s->now();
-                if (n_done) ++*n_done;
+                if (sh.phase == xrt::CHUNK_COMPUTE && sh.split > 1) {
+                    start_phase(s, sh, xrt::CHUNK_REDUCE);  // every part sum is in the arena
+                    s->admitted.push_back(sh.ticket);
+                } else {
+                    sh.state = XRT_SHOT_DONE;
+                    sh.t_done = s->now();
+                    if (n_done) ++*n_done;
+                }
             }
         } else {
             s->inflight[w++] = f;
@@ -242,6 +275,13 @@ xrt_status admit(xrt_server *s)
         d.src_rel = d.mats_rel + 9 * sizeof(double) * (size_t)d.p.n_rot;
         d.image_off = doff;
         d.image_bytes = sh.image_bytes;
+        d.partial_off = doff + align_up(sh.image_bytes);
+        d.partial_bytes = sh.part_bytes;
+        if (d.p.split != sh.split) {
+            s->arena->release(doff, sh.footprint);
+            s->harena->release(hoff, sh.desc_bytes);
+            return fail(XRT_EINVAL, "internal: split %d at admission, %d at submission", d.p.split, sh.split);
+        }
         std::memcpy(s->host_arena + hoff, &d, sizeof d);
         std::memcpy(s->host_arena + hoff + d.mats_rel, host.data(), sizeof(double) * host.size());
         sh.desc_off = hoff;
@@ -249,17 +289,10 @@ xrt_status admit(xrt_server *s)
         sh.state = XRT_SHOT_RUNNING;
         sh.t_admit = s->now();
         sh.n_tiles = d.p.n_tiles;
-        // chunk size: about CHUNK_TERMS pixel-terms (a few ms of one
-        // workgroup, so a shot admitted later waits at most that long for a
-        // workgroup, and the last chunks of a shot end close together), and
-        // no more tiles than spread the shot over every workgroup
-        const uint64_t per_tile = (uint64_t)TILE_PIXELS * (uint64_t)d.p.O * (uint64_t)d.p.O * (uint64_t)d.p.T *
-                                  (uint64_t)d.p.n_src * (uint64_t)d.p.n_rot;
-        const uint64_t by_cost = std::max<uint64_t>(1, CHUNK_TERMS / std::max<uint64_t>(per_tile, 1));
-        const uint64_t by_spread = ((uint64_t)sh.n_tiles + s->n_wg - 1) / s->n_wg;
-        sh.chunk_tiles = (int32_t)std::max<uint64_t>(
-            1, std::min<uint64_t>({by_cost, by_spread, (uint64_t)xrt::SERVE_MAX_CHUNK}));
-        sh.chunks_total = (sh.n_tiles + sh.chunk_tiles - 1) / sh.chunk_tiles;
+        sh.terms_per_pixel = (uint64_t)d.p.O * (uint64_t)d.p.O * (uint64_t)d.p.T * (uint64_t)d.p.n_src *
+                             (uint64_t)d.p.n_rot;
+        start_phase(s, sh, xrt::CHUNK_COMPUTE);
+        sh.work_published = s->vtime;  // it competes from now on, not from the start
         s->resident++;
         s->admitted.push_back(sh.ticket);
         s->queue.pop_front();
@@ -267,32 +300,44 @@ xrt_status admit(xrt_server *s)
     return XRT_OK;
 }
 
-// (3) publication: one chunk per admitted shot per round, while fewer than
-// two chunks per workgroup are in flight.  The shallow queue keeps a shot
-// admitted later from waiting behind the whole of an earlier large one: its
-// chunks enter the ring as soon as earlier chunks finish.
+// (3) publication, while fewer than two chunks per workgroup are in flight:
+// the next chunk always comes from the admitted shot with the least work
+// published so far (pixel-terms; ties to the earlier ticket), so resident
+// shots share the device evenly by work whatever their chunk sizes, and a
+// small shot admitted later is not stuck behind a large one.  The shallow
+// queue lets a newly admitted shot's chunks enter the ring as soon as earlier
+// chunks finish.
 void publish(xrt_server *s)
 {
     const size_t depth = std::min<size_t>(RING - 1, 2 * (size_t)s->n_wg);
     bool any = false;
     while (s->inflight.size() < depth && !s->admitted.empty()) {
-        if (s->rr >= s->admitted.size()) s->rr = 0;
-        Shot &sh = s->shots[s->admitted[s->rr]];
+        size_t best = 0;
+        for (size_t i = 1; i < s->admitted.size(); ++i) {
+            const Shot &a = s->shots[s->admitted[i]], &b = s->shots[s->admitted[best]];
+            if (a.work_published < b.work_published ||
+                (a.work_published == b.work_published && a.ticket < b.ticket))
+                best = i;
+        }
+        Shot &sh = s->shots[s->admitted[best]];
+        s->vtime = sh.work_published;
         const uint64_t seq = s->tail;
         xrt::ServeChunk &c = s->ring[seq % RING];
         c.desc_off = sh.desc_off;
-        c.tile0 = sh.next_tile;
-        c.n_tiles = std::min(sh.chunk_tiles, sh.n_tiles - sh.next_tile);
+        c.tile0 = sh.next_unit;
+        c.n_tiles = std::min(sh.chunk_units, sh.n_units - sh.next_unit);
         c.seq1 = (uint32_t)(seq + 1);
         c.shot = (uint32_t)sh.ticket ? (uint32_t)sh.ticket : 1u;
-        sh.next_tile += c.n_tiles;
+        c.kind = sh.phase;
+        c.pad = 0;
+        sh.next_unit += c.n_tiles;
+        // a reduce chunk reads K values per pixel: count it as K terms
+        sh.work_published += (double)c.n_tiles * TILE_PIXELS *
+                             (sh.phase == xrt::CHUNK_COMPUTE ? (double)sh.terms_per_pixel / sh.split : sh.split);
         s->inflight.push_back({seq, sh.ticket});
         s->tail++;
         any = true;
-        if (sh.next_tile >= sh.n_tiles)
-            s->admitted.erase(s->admitted.begin() + s->rr);
-        else
-            s->rr++;
+        if (sh.next_unit >= sh.n_units) s->admitted.erase(s->admitted.begin() + best);
     }
     if (any) __atomic_store_n(&s->ctrl->tail, s->tail, __ATOMIC_RELEASE);
 }
@@ -418,7 +463,12 @@ xrt_status xrt_server_submit(xrt_server *s, const xrt_detector *det, const xrt_b
     const uint64_t tables = sizeof(double) * (9 * (uint64_t)xtal->n_phi * xtal->n_mos + xrt::SRC_STRIDE * (uint64_t)beam->n_src);
     sh.desc_bytes = align_up(align_up(sizeof(xrt::ShotDesc)) + tables);
     sh.image_bytes = n_pix * (s->desc.out_dtype == XRT_F64 ? 8 : 4);
-    sh.footprint = align_up(sh.image_bytes);
+    // split sums keep their part sums in the arena after the image
+    sh.split = xrt::host::split_of(det, beam, xtal);
+    const uint64_t n_tiles = (uint64_t)((det->roi_f1 - det->roi_f0 + 15) / 16) *
+                             (uint64_t)((det->roi_s1 - det->roi_s0 + 15) / 16);
+    sh.part_bytes = sh.split > 1 ? sizeof(double) * n_tiles * (uint64_t)sh.split * TILE_PIXELS : 0;
+    sh.footprint = align_up(sh.image_bytes) + align_up(sh.part_bytes);
     if (sh.footprint > s->desc.hbm_budget)
         return fail(XRT_ERANGE, "shot needs %llu bytes, more than the server's budget %llu",
                     (unsigned long long)sh.footprint, (unsigned long long)s->desc.hbm_budget);

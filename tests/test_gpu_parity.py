@@ -114,10 +114,21 @@ def test_full_sampled_pixels(full):
     assert r32["zeros_ok"] and r32["max_rel"] <= MIXED_TOL
 
 
+def split_of(shot, n_tiles):
+    """The split factor the library applies (its documented rule)."""
+    n_outer = shot.oversample ** 2 * shot.n_layers * shot.n_src
+    if n_tiles >= 2048:
+        return 1
+    k = min(-(-2048 // n_tiles), n_outer, n_outer * shot.n_phi * shot.n_mos // 1024, 64)
+    return max(k, 1)
+
+
 @pytest.mark.parametrize("roi", [(1210, 1255, 1245, 1282), (2420, 2463, 0, 29)])
 def test_full_crops(full, roi):
     """Crops at the beam centre and at a corner (ragged tiles), as separate
-    ROI launches and as windows of the full-size image."""
+    ROI launches (split sums: few tiles) and as windows of the full-size image
+    (whole sums); both against the oracle, and against each other to the
+    rounding of a different summation order."""
     shot, fh, img64, img32 = full
     ref = o.simulate(shot.replace(roi=roi))
     f0, f1, s0, s1 = roi
@@ -128,7 +139,30 @@ def test_full_crops(full, roi):
         r = compare(x, ref)
         say(roi, name, r)
         assert r["zeros_ok"] and r["max_rel"] <= tol
-    assert np.array_equal(win64, roi64)
+    f0, f1, s0, s1 = roi
+    say("split factor of the crop", split_of(shot, -(-(f1 - f0) // 16) * -(-(s1 - s0) // 16)))
+    nz = win64 > 0
+    assert np.array_equal(nz, roi64 > 0)
+    assert np.max(np.abs(roi64[nz] - win64[nz]) / win64[nz]) <= 1e-13
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_split_sums(full, precision, tol):
+    """A 40 x 40 ROI of the full shot (9 tiles, so each pixel's 1200 outer
+    iterations are cut into 58 parts): parity with the oracle, identical bits
+    on a second call, and the accumulate option through the reduction."""
+    shot, fh, img64, img32 = full
+    roi = (1200, 1240, 1250, 1290)
+    assert split_of(shot, 9) == 58
+    ref = o.simulate(shot.replace(roi=roi))
+    a = xrt.simulate(shot, fh, precision=precision, roi=roi, out_dtype=torch.float64)
+    b = xrt.simulate(shot, fh, precision=precision, roi=roi, out_dtype=torch.float64)
+    r = compare(a.cpu().numpy(), ref)
+    say("split", precision, r)
+    assert r["zeros_ok"] and r["max_rel"] <= tol
+    assert torch.equal(a, b)
+    xrt.simulate(shot, fh, precision=precision, roi=roi, out=b, accumulate=True)
+    assert torch.equal(b, 2 * a)
 
 
 def test_full_gauss_sampled():
