@@ -179,6 +179,49 @@ def serving_bench(n_cap=60, n_open=150, load=0.8):
             "closed_loop": closed, "poisson": opened, "load": load}
 
 
+def serving_sweep(n_cap=200, n_open=1000, loads=(0.5, 0.8, 0.95), small_budget=256 << 20):
+    """The served stream at several offered loads: capacity from n_cap shots
+    submitted at once, then n_open Poisson arrivals at each load x capacity;
+    finally the capacity again under a small HBM budget, which admits fewer
+    shots at once.  Several minutes of GPU time: not part of the default run."""
+    import numpy as np
+    import synth
+    from paper_2205_07976_amd import serve, xrt
+    base = synth.full_shot()
+    fh = xrt.Fhkl.from_shot(base)
+    rng = np.random.default_rng(14)
+
+    def progress(tag, n):
+        def cb(i, t, count=[0]):
+            count[0] += 1
+            if count[0] % 100 == 0 or count[0] == n:
+                log(f"  {tag}: {count[0]}/{n} shots done")
+        return cb
+
+    out = {"workload": "served stream: log-uniform ROI, 1-100 sources, 1-200 domains, N in [5,40], mixed"}
+    for name, budget in (("budget_16GiB", 16 << 30), (f"budget_{small_budget >> 20}MiB", small_budget)):
+        srv = xrt.Server(fh, hbm_budget=budget, max_resident=64, precision="mixed")
+        cap_shots = [synth.served_shot(rng, base.F, base.hkl_min) for _ in range(n_cap)]
+        serve.run_stream(srv, cap_shots[:2], np.zeros(2))
+        closed = serve.summarize(serve.run_stream(srv, cap_shots, np.zeros(n_cap),
+                                                  on_done=progress(f"{name} capacity", n_cap)), cap_shots)
+        log(f"{name}: capacity {closed['images_per_s']:.2f} img/s ({closed['Gterm_per_s']:.0f} Gterm/s)")
+        res = {"closed_loop": closed}
+        if name == "budget_16GiB":
+            for load in loads:
+                shots = [synth.served_shot(rng, base.F, base.hkl_min) for _ in range(n_open)]
+                rate = load * closed["images_per_s"]
+                arr = serve.poisson_arrivals(np.random.default_rng(int(load * 100)), n_open, rate)
+                opened = serve.summarize(serve.run_stream(srv, shots, arr, on_done=progress(f"load {load}", n_open)),
+                                         shots, rate)
+                log(f"{name} at {load:.2f} load: p50 {opened['p50_ms']:.1f} ms p99 {opened['p99_ms']:.1f} ms, "
+                    f"{opened['Gterm_per_s']:.0f} Gterm/s")
+                res[f"poisson_{load:.2f}"] = opened
+        srv.close()
+        out[name] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +231,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the regions-of-interest adjoint")
     ap.add_argument("--no-serve", action="store_true", help="skip the served shot stream")
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="also serve 1000 Poisson shots at 0.5, 0.8 and 0.95 x capacity and measure the "
+                         "capacity under a 256 MiB budget (several minutes)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="finish with one device-to-device copy of this many MiB (a kernel of known "
                          "traffic that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -246,6 +292,8 @@ def main():
         res["serving"] = serving_bench()
         res["p50_shot_latency_ms"] = res["serving"]["poisson"]["p50_ms"]
         res["p99_shot_latency_ms"] = res["serving"]["poisson"]["p99_ms"]
+    if args.serve_sweep:
+        res["serving_sweep"] = serving_sweep()
 
     if args.copy_mib:
         n = args.copy_mib * (1 << 20) // 4
