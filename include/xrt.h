@@ -89,8 +89,11 @@ typedef struct xrt_detector {
     int32_t n_fast, n_slow;        /* detector size, pixels (>= 1) */
     double pixel;                  /* pixel pitch, m (> 0) */
     double distance;               /* sample to front face along odet, m (> 0) */
-    double beam_f, beam_s;         /* position of the detector origin's offset:
-                                      the point Fp = Sp = 0, m */
+    double beam_f, beam_s;         /* m, along fdet and sdet from the outer corner
+                                      of pixel (0, 0) to the foot of the
+                                      perpendicular from the sample onto the
+                                      detector (Fp = Sp = 0; the direct-beam
+                                      spot when the beam runs along odet) */
     double fdet[3], sdet[3], odet[3]; /* fast, slow axes and normal (unit) */
     int32_t oversample;            /* O >= 1 sub-pixels per axis */
     int32_t n_layers;              /* sensor layers >= 1 */
