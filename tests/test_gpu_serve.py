@@ -162,3 +162,61 @@ def test_run_stream_poisson():
         assert np.array_equal(res["images"][i].cpu().numpy(),
                               xrt.simulate(shots[i], fh, precision="mixed").cpu().numpy())
     srv.close()
+
+
+def heavy_small_shots(n, seed):
+    """Small ROIs with many terms per pixel: their sums are split into parts
+    (compute chunks, then reduce chunks on the server)."""
+    base = synth.full_shot()
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        s = synth.served_shot(rng, base.F, base.hkl_min)
+        w, h = int(rng.integers(16, 72)), int(rng.integers(16, 72))
+        f0, s0 = int(rng.integers(900, 1500)), int(rng.integers(900, 1500))
+        n_src, n_mos = int(rng.integers(30, 101)), int(rng.integers(8, 25))
+        s = s.replace(roi=(f0, f0 + w, s0, s0 + h), src_dir=s.src_dir[:n_src].copy(),
+                      src_lambda=s.src_lambda[:n_src].copy(),
+                      src_weight=s.src_weight[:n_src] / s.src_weight[:n_src].sum(), umats=s.umats[:n_mos].copy())
+        out.append(s)
+    return base, out
+
+
+def expected_split(shot):
+    f0, f1, s0, s1 = shot.roi
+    tiles = -(-(f1 - f0) // 16) * -(-(s1 - s0) // 16)
+    n_outer = shot.oversample ** 2 * shot.n_layers * shot.n_src
+    if tiles >= 2048:
+        return 1
+    return max(1, min(-(-2048 // tiles), n_outer, n_outer * shot.n_phi * shot.n_mos // 1024, 64))
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_served_split_shots(precision):
+    """Split shots (part sums in the arena, reduce chunks after every part is
+    done) beside whole-sum shots: each image equals the standalone call's bit
+    for bit, in the mix and alone; one split image against the oracle."""
+    base, heavy = heavy_small_shots(4, seed=21)
+    _, light = small_served_shots(4, seed=22, max_side=64)
+    shots = [x for pair in zip(heavy, light) for x in pair]
+    splits = [expected_split(s) for s in shots]
+    say("split factors", splits)
+    assert max(splits) > 1 and min(splits) == 1
+    fh = xrt.Fhkl.from_shot(base)
+    ref = [xrt.simulate(s, fh, precision=precision).cpu().numpy() for s in shots]
+    srv = xrt.Server(fh, hbm_budget=256 << 20, precision=precision)
+    tickets = [srv.submit(s) for s in shots]
+    drain(srv, tickets)
+    for i, t in enumerate(tickets):
+        assert np.array_equal(srv.image(t).cpu().numpy(), ref[i]), f"shot {i} (split {splits[i]}) differs in the mix"
+        srv.release(t)
+    for i in (0, 2):
+        t = srv.submit(shots[i])
+        drain(srv, [t])
+        assert np.array_equal(srv.image(t).cpu().numpy(), ref[i]), f"shot {i} differs alone"
+        srv.release(t)
+    srv.close()
+    if precision == "mixed":
+        r = compare(ref[0], o.simulate(shots[0]))
+        say("split shot vs oracle", r)
+        assert r["zeros_ok"] and r["max_rel"] <= 1e-5
