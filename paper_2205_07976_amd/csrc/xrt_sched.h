@@ -1,0 +1,284 @@
+// xrt_sched.h -- the shot server's scheduling logic, free of any device code:
+// arena allocation, admission in arrival order by HBM footprint and resident
+// slots, chunking of each shot's work, the order chunks are published in, and
+// the bookkeeping that turns finished chunks into finished phases and shots.
+// xrt_server.cpp drives it against the GPU (descriptors in pinned memory, a
+// ring of chunk records, done flags written by the persistent kernel); the
+// CPU tests drive it against a simulated device.  Not part of the public ABI.
+#pragma once
+
+#include <stdint.h>
+
+#include <algorithm>
+#include <deque>
+#include <iterator>
+#include <map>
+#include <unordered_map>
+#include <vector>
+
+namespace xrt {
+namespace sched {
+
+constexpr uint64_t ALIGN = 256;
+constexpr int TILE_PIXELS = 256;            // 16 x 16 pixels per tile
+constexpr uint64_t CHUNK_TERMS = 1u << 20;  // pixel-terms a compute chunk aims at
+constexpr int MAX_CHUNK = 64;               // work units per chunk
+enum { PHASE_COMPUTE = 0, PHASE_REDUCE = 1 };
+enum { QUEUED = 0, RUNNING = 1, DONE = 2 };
+
+inline uint64_t align_up(uint64_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+// First-fit allocator over [0, size) with coalescing of freed neighbours.
+class Arena {
+  public:
+    explicit Arena(uint64_t size) : size_(size) { free_[0] = size; }
+    bool alloc(uint64_t n, uint64_t *off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *off = it->first;
+                const uint64_t rest = it->second - n, start = it->first + n;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t n)
+    {
+        if (n == 0) return;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    uint64_t size() const { return size_; }
+    const std::map<uint64_t, uint64_t> &free_blocks() const { return free_; }
+
+  private:
+    uint64_t size_;
+    std::map<uint64_t, uint64_t> free_;  // offset -> length
+};
+
+// What the scheduler knows of a shot.  The caller fills the first block at
+// submission; the scheduler owns the rest.
+struct Work {
+    uint64_t ticket = 0;
+    uint64_t footprint = 0;        // device arena bytes (image, then part sums)
+    uint64_t desc_bytes = 0;       // host arena bytes (descriptor and tables)
+    int32_t n_tiles = 0;           // 16 x 16 tiles of the region
+    int32_t split = 1;             // parts per pixel sum (1: whole sums)
+    uint64_t terms_per_pixel = 0;
+    // owned by the scheduler
+    int state = QUEUED;
+    uint64_t dev_off = 0, host_off = 0;
+    // current phase: PHASE_COMPUTE over units tile * split + part, then, for
+    // split sums, PHASE_REDUCE over tiles once every part is done
+    int32_t phase = PHASE_COMPUTE;
+    int32_t n_units = 0, chunk_units = 1, next_unit = 0;
+    int64_t chunks_total = 0, chunks_done = 0;
+    double work_published = 0;     // pixel-terms of the chunks published so far
+};
+
+// One published chunk: units [unit0, unit0 + n_units) of a shot's phase.
+struct Chunk {
+    uint64_t seq;                  // publication number
+    uint64_t ticket;
+    int32_t kind;                  // PHASE_COMPUTE or PHASE_REDUCE
+    int32_t unit0, n_units;
+};
+
+class Scheduler {
+  public:
+    // dev_bytes / host_bytes: arena sizes; n_wg: workgroups of the persistent
+    // kernel (chunk sizing and the publication depth); ring: capacity of the
+    // ring of chunk records.
+    Scheduler(uint64_t dev_bytes, uint64_t host_bytes, int max_resident, int n_wg, uint32_t ring)
+        : dev_(dev_bytes), host_(host_bytes), max_resident_(max_resident), n_wg_(std::max(n_wg, 1)),
+          depth_(std::min<size_t>(ring - 1, 2 * (size_t)std::max(n_wg, 1)))
+    {
+    }
+
+    // Queue a shot (footprint, desc_bytes, n_tiles, split, terms_per_pixel set).
+    void submit(const Work &w)
+    {
+        Work &x = work_[w.ticket] = w;
+        x.state = QUEUED;
+        queue_.push_back(w.ticket);
+    }
+
+    // Admission in arrival order: while the head of the queue fits both arenas
+    // and a resident slot is free, allocate its space, call
+    // prepare(work) -> int (0: admitted; else the error, the space is freed
+    // and admission stops) and start its first phase.  A head that does not
+    // fit blocks the ones behind it (no overtaking).  Returns 0 or the error.
+    template <class Prepare>
+    int admit(Prepare prepare)
+    {
+        while (!queue_.empty() && resident_ < (uint64_t)max_resident_) {
+            Work &w = work_[queue_.front()];
+            uint64_t doff = 0, hoff = 0;
+            if (!dev_.alloc(w.footprint, &doff)) break;
+            if (!host_.alloc(w.desc_bytes, &hoff)) {
+                dev_.release(doff, w.footprint);
+                break;
+            }
+            w.dev_off = doff;
+            w.host_off = hoff;
+            const int st = prepare(w);
+            if (st) {
+                dev_.release(doff, w.footprint);
+                host_.release(hoff, w.desc_bytes);
+                return st;
+            }
+            w.state = RUNNING;
+            start_phase(w, PHASE_COMPUTE);
+            w.work_published = vtime_;  // it competes from now on, not from the start
+            resident_++;
+            admitted_.push_back(w.ticket);
+            queue_.pop_front();
+        }
+        return 0;
+    }
+
+    // Publication while fewer than `depth` chunks are in flight: the next
+    // chunk always comes from the admitted shot with the least work published
+    // so far (pixel-terms; ties to the earlier ticket), so resident shots
+    // share the device evenly by work whatever their chunk sizes, and a shot
+    // admitted later joins at the current level.  emit(const Chunk &, Work &)
+    // writes the record.  Returns the number of chunks published.
+    template <class Emit>
+    size_t publish(Emit emit)
+    {
+        size_t n = 0;
+        while (inflight_.size() < depth_ && !admitted_.empty()) {
+            size_t best = 0;
+            for (size_t i = 1; i < admitted_.size(); ++i) {
+                const Work &a = work_[admitted_[i]], &b = work_[admitted_[best]];
+                if (a.work_published < b.work_published ||
+                    (a.work_published == b.work_published && a.ticket < b.ticket))
+                    best = i;
+            }
+            Work &w = work_[admitted_[best]];
+            vtime_ = w.work_published;
+            Chunk c;
+            c.seq = tail_++;
+            c.ticket = w.ticket;
+            c.kind = w.phase;
+            c.unit0 = w.next_unit;
+            c.n_units = std::min(w.chunk_units, w.n_units - w.next_unit);
+            w.next_unit += c.n_units;
+            // a reduce chunk reads K values per pixel: count it as K terms
+            w.work_published += (double)c.n_units * TILE_PIXELS *
+                                (w.phase == PHASE_COMPUTE ? (double)w.terms_per_pixel / w.split : w.split);
+            inflight_.push_back({c.seq, c.ticket});
+            emit(c, w);
+            ++n;
+            if (w.next_unit >= w.n_units) admitted_.erase(admitted_.begin() + best);
+        }
+        return n;
+    }
+
+    // Finished chunks: is_done(seq) says whether chunk `seq` is done.  A
+    // compute phase of a split shot that completes starts its reduce phase;
+    // any other completed phase finishes the shot, whose ticket is appended to
+    // *finished.
+    template <class IsDone>
+    void collect(IsDone is_done, std::vector<uint64_t> *finished)
+    {
+        size_t k = 0;
+        for (size_t i = 0; i < inflight_.size(); ++i) {
+            const InFlight f = inflight_[i];
+            if (!is_done(f.seq)) {
+                inflight_[k++] = f;
+                continue;
+            }
+            Work &w = work_[f.ticket];
+            if (++w.chunks_done == w.chunks_total) {
+                if (w.phase == PHASE_COMPUTE && w.split > 1) {
+                    start_phase(w, PHASE_REDUCE);  // every part sum is in the arena
+                    admitted_.push_back(w.ticket);
+                } else {
+                    w.state = DONE;
+                    if (finished) finished->push_back(w.ticket);
+                }
+            }
+        }
+        inflight_.resize(k);
+    }
+
+    // Forget a finished shot and free its space.  Returns false if the shot
+    // is unknown or not done.
+    bool release(uint64_t ticket)
+    {
+        auto it = work_.find(ticket);
+        if (it == work_.end() || it->second.state != DONE) return false;
+        dev_.release(it->second.dev_off, it->second.footprint);
+        host_.release(it->second.host_off, it->second.desc_bytes);
+        resident_--;
+        work_.erase(it);
+        return true;
+    }
+
+    const Work *find(uint64_t ticket) const
+    {
+        auto it = work_.find(ticket);
+        return it == work_.end() ? nullptr : &it->second;
+    }
+    size_t in_flight() const { return inflight_.size(); }
+    size_t depth() const { return depth_; }
+    uint64_t resident() const { return resident_; }
+    uint64_t published() const { return tail_; }
+    const Arena &dev_arena() const { return dev_; }
+    const Arena &host_arena() const { return host_; }
+
+  private:
+    struct InFlight {
+        uint64_t seq, ticket;
+    };
+
+    // Chunking of a phase: compute chunks hold about CHUNK_TERMS pixel-terms
+    // (a few ms of one workgroup, so a shot admitted later waits at most that
+    // long for a workgroup, and the last chunks of a shot end close together)
+    // and no more units than spread the phase over every workgroup; reduce
+    // chunks (K loads per pixel) are spread the same way.
+    void start_phase(Work &w, int32_t phase)
+    {
+        w.phase = phase;
+        w.n_units = phase == PHASE_COMPUTE ? w.n_tiles * w.split : w.n_tiles;
+        const uint64_t by_spread = ((uint64_t)w.n_units + n_wg_ - 1) / n_wg_;
+        uint64_t by_cost = (uint64_t)MAX_CHUNK;
+        if (phase == PHASE_COMPUTE) {
+            const uint64_t per_unit = std::max<uint64_t>(1, TILE_PIXELS * w.terms_per_pixel / (uint64_t)w.split);
+            by_cost = std::max<uint64_t>(1, CHUNK_TERMS / per_unit);
+        }
+        w.chunk_units = (int32_t)std::max<uint64_t>(1, std::min<uint64_t>({by_cost, by_spread, (uint64_t)MAX_CHUNK}));
+        w.next_unit = 0;
+        w.chunks_total = (w.n_units + w.chunk_units - 1) / w.chunk_units;
+        w.chunks_done = 0;
+    }
+
+    Arena dev_, host_;
+    int max_resident_;
+    int n_wg_;
+    size_t depth_;
+    uint64_t resident_ = 0, tail_ = 0;
+    double vtime_ = 0;  // published work of the shot served last
+    std::deque<uint64_t> queue_;         // submitted, not admitted (FIFO)
+    std::vector<uint64_t> admitted_;     // admitted, with units of the current phase left to publish
+    std::vector<InFlight> inflight_;     // published, not done
+    std::unordered_map<uint64_t, Work> work_;
+};
+
+}  // namespace sched
+}  // namespace xrt

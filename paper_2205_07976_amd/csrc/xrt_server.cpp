@@ -38,82 +38,34 @@
 #include <vector>
 
 #include "../../include/xrt.h"
-#include "xrt_internal.h"
 #include "xrt_host.h"
+#include "xrt_internal.h"
+#include "xrt_sched.h"
 
 using xrt::host::fail;
 using xrt::host::hip_fail;
 
 namespace {
 
-constexpr uint64_t ALIGN = 256;
+using xrt::sched::align_up;
 constexpr uint32_t RING = 1u << 16;
-constexpr int TILE_PIXELS = 256;           // 16 x 16 pixels per tile
-constexpr uint64_t CHUNK_TERMS = 1u << 20;  // pixel-terms a chunk aims at
+static_assert(xrt::sched::PHASE_COMPUTE == xrt::CHUNK_COMPUTE && xrt::sched::PHASE_REDUCE == xrt::CHUNK_REDUCE,
+              "chunk kinds");
+static_assert(xrt::sched::MAX_CHUNK == xrt::SERVE_MAX_CHUNK, "units per chunk");
+static_assert(xrt::sched::TILE_PIXELS == 256, "tile of the kernels");
+static_assert(xrt::sched::QUEUED == XRT_SHOT_QUEUED && xrt::sched::RUNNING == XRT_SHOT_RUNNING &&
+                  xrt::sched::DONE == XRT_SHOT_DONE,
+              "shot states");
 
-uint64_t align_up(uint64_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
-
-// First-fit allocator over [0, size) with coalescing.
-class Arena {
-  public:
-    explicit Arena(uint64_t size) { free_[0] = size; }
-    bool alloc(uint64_t n, uint64_t *off)
-    {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= n) {
-                *off = it->first;
-                const uint64_t rest = it->second - n, start = it->first + n;
-                free_.erase(it);
-                if (rest) free_[start] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(uint64_t off, uint64_t n)
-    {
-        auto it = free_.emplace(off, n).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-
-  private:
-    std::map<uint64_t, uint64_t> free_;
-};
-
+// What the server keeps of a shot beside the scheduler's record: the shot
+// itself (read again at admission), its image size and its times.
 struct Shot {
-    uint64_t ticket = 0;
-    int state = XRT_SHOT_QUEUED;
     xrt_detector det{};
     xrt_beam beam{};
     xrt_crystal xtal{};
     std::vector<double> dir, lam, weight, umats;
-    uint64_t desc_bytes = 0, image_bytes = 0, part_bytes = 0, footprint = 0;
-    uint64_t desc_off = 0, image_off = 0;  // in the host and device arenas
-    int32_t n_tiles = 0, split = 1;
-    uint64_t terms_per_pixel = 0;
-    // the current phase: CHUNK_COMPUTE over units tile * split + part, then,
-    // for split sums, CHUNK_REDUCE over tiles once every part is done
-    int32_t phase = xrt::CHUNK_COMPUTE;
-    int32_t n_units = 0, chunk_units = 1, next_unit = 0;
-    int64_t chunks_total = 0, chunks_done = 0;
-    double work_published = 0;  // pixel-terms of the chunks published so far
+    uint64_t image_bytes = 0, part_bytes = 0;
     double t_submit = 0, t_admit = -1, t_done = -1;
-};
-
-struct InFlight {
-    uint64_t seq;
-    uint64_t ticket;
 };
 
 }  // namespace
@@ -123,10 +75,9 @@ struct xrt_server {
     int device = 0;
     xrt_server_desc desc{};
     const xrt_fhkl *fhkl = nullptr;
-    Arena *arena = nullptr;       // device arena: images (the HBM budget)
-    Arena *harena = nullptr;      // host arena: descriptors and tables
-    char *dev_arena = nullptr;
-    char *host_arena = nullptr;
+    xrt::sched::Scheduler *sched = nullptr;  // arenas, admission, chunks, publication order
+    char *dev_arena = nullptr;               // images and part sums (the HBM budget)
+    char *host_arena = nullptr;              // descriptors and tables (pinned)
     uint64_t host_bytes = 0;
     // device control block: [0] chunks claimed, [1] time of the latest
     // finished chunk, then two 32-bit words: busy workgroups, exit flag
@@ -138,11 +89,7 @@ struct xrt_server {
     hipEvent_t kernel_done = nullptr;
     bool launched = false;
     int n_wg = 0;
-    uint64_t next_ticket = 1, tail = 0, resident = 0;
-    std::deque<uint64_t> queue;                    // submitted, not admitted (FIFO)
-    std::vector<uint64_t> admitted;                // admitted with tiles left to publish
-    std::vector<InFlight> inflight;                // published chunks not yet done
-    double vtime = 0;                              // published work of the shot served last
+    uint64_t next_ticket = 1;
     std::unordered_map<uint64_t, Shot> shots;
     std::chrono::steady_clock::time_point t0;
 
@@ -179,8 +126,7 @@ void free_server(xrt_server *s)
     if (s->ring) (void)hipHostFree(s->ring);
     if (s->done) (void)hipHostFree(s->done);
     if (s->host_arena) (void)hipHostFree(s->host_arena);
-    delete s->arena;
-    delete s->harena;
+    delete s->sched;
     delete s;
 }
 
@@ -197,68 +143,24 @@ bool kernel_running(xrt_server *s, hipError_t *err)
     return false;
 }
 
-// Chunking of a shot's current phase.  Compute chunks hold about
-// CHUNK_TERMS pixel-terms (a few ms of one workgroup, so a shot admitted later
-// waits at most that long for a workgroup, and the last chunks of a shot end
-// close together) and no more units than spread the phase over every
-// workgroup; reduce chunks (K loads per pixel) are spread the same way.
-void start_phase(xrt_server *s, Shot &sh, int32_t phase)
-{
-    sh.phase = phase;
-    sh.n_units = phase == xrt::CHUNK_COMPUTE ? sh.n_tiles * sh.split : sh.n_tiles;
-    const uint64_t by_spread = ((uint64_t)sh.n_units + s->n_wg - 1) / s->n_wg;
-    uint64_t by_cost = (uint64_t)xrt::SERVE_MAX_CHUNK;
-    if (phase == xrt::CHUNK_COMPUTE) {
-        const uint64_t per_unit = std::max<uint64_t>(1, TILE_PIXELS * sh.terms_per_pixel / (uint64_t)sh.split);
-        by_cost = std::max<uint64_t>(1, CHUNK_TERMS / per_unit);
-    }
-    sh.chunk_units = (int32_t)std::max<uint64_t>(
-        1, std::min<uint64_t>({by_cost, by_spread, (uint64_t)xrt::SERVE_MAX_CHUNK}));
-    sh.next_unit = 0;
-    sh.chunks_total = (sh.n_units + sh.chunk_units - 1) / sh.chunk_units;
-    sh.chunks_done = 0;
-}
-
 // (1) done flags -> finished chunks -> finished phases and shots.
 void collect(xrt_server *s, int32_t *n_done)
 {
-    size_t w = 0;
-    for (size_t i = 0; i < s->inflight.size(); ++i) {
-        const InFlight f = s->inflight[i];
-        const uint32_t flag = __atomic_load_n(&s->done[f.seq % RING], __ATOMIC_ACQUIRE);
-        if (flag == (uint32_t)(f.seq + 1)) {
-            Shot &sh = s->shots[f.ticket];
-            if (++sh.chunks_done == sh.chunks_total) {
-                if (sh.phase == xrt::CHUNK_COMPUTE && sh.split > 1) {
-                    start_phase(s, sh, xrt::CHUNK_REDUCE);  // every part sum is in the arena
-                    s->admitted.push_back(sh.ticket);
-                } else {
-                    sh.state = XRT_SHOT_DONE;
-                    sh.t_done = s->now();
-                    if (n_done) ++*n_done;
-                }
-            }
-        } else {
-            s->inflight[w++] = f;
-        }
-    }
-    s->inflight.resize(w);
+    std::vector<uint64_t> finished;
+    s->sched->collect([s](uint64_t seq) { return __atomic_load_n(&s->done[seq % RING], __ATOMIC_ACQUIRE) == (uint32_t)(seq + 1); },
+                      &finished);
+    for (uint64_t t : finished) s->shots[t].t_done = s->now();
+    if (n_done) *n_done = (int32_t)finished.size();
 }
 
-// (2) admission: device memory for the image, host memory for the
-// descriptor and a resident slot, in arrival order.  The descriptor and tables
-// are written straight into the pinned host arena: no device copy is needed,
-// so admission never waits for the running persistent kernel.
+// (2) admission (in arrival order, by device-arena footprint and resident
+// slots; the scheduler's rule): the descriptor and tables are written straight
+// into the pinned host arena, so admission needs no device copy and never
+// waits for the running persistent kernel.
 xrt_status admit(xrt_server *s)
 {
-    while (!s->queue.empty() && s->resident < (uint64_t)s->desc.max_resident) {
-        Shot &sh = s->shots[s->queue.front()];
-        uint64_t doff = 0, hoff = 0;
-        if (!s->arena->alloc(sh.footprint, &doff)) break;
-        if (!s->harena->alloc(sh.desc_bytes, &hoff)) {
-            s->arena->release(doff, sh.footprint);
-            break;
-        }
+    return (xrt_status)s->sched->admit([s](xrt::sched::Work &w) -> int {
+        Shot &sh = s->shots[w.ticket];
         sh.beam.dir = sh.dir.data();
         sh.beam.lambda = sh.lam.data();
         sh.beam.weight = sh.weight.data();
@@ -266,80 +168,37 @@ xrt_status admit(xrt_server *s)
         std::vector<double> host;
         xrt::ShotDesc d;
         xrt_status st = xrt::host::served_descriptor(&sh.det, &sh.beam, &sh.xtal, s->fhkl, s->desc.out_dtype, &d, host);
-        if (st) {
-            s->arena->release(doff, sh.footprint);
-            s->harena->release(hoff, sh.desc_bytes);
-            return st;
-        }
+        if (st) return st;
+        if (d.p.split != w.split || d.p.n_tiles != w.n_tiles)
+            return fail(XRT_EINVAL, "internal: shot plan differs between submission and admission");
         d.mats_rel = align_up(sizeof(xrt::ShotDesc));
         d.src_rel = d.mats_rel + 9 * sizeof(double) * (size_t)d.p.n_rot;
-        d.image_off = doff;
+        d.image_off = w.dev_off;
         d.image_bytes = sh.image_bytes;
-        d.partial_off = doff + align_up(sh.image_bytes);
+        d.partial_off = w.dev_off + align_up(sh.image_bytes);
         d.partial_bytes = sh.part_bytes;
-        if (d.p.split != sh.split) {
-            s->arena->release(doff, sh.footprint);
-            s->harena->release(hoff, sh.desc_bytes);
-            return fail(XRT_EINVAL, "internal: split %d at admission, %d at submission", d.p.split, sh.split);
-        }
-        std::memcpy(s->host_arena + hoff, &d, sizeof d);
-        std::memcpy(s->host_arena + hoff + d.mats_rel, host.data(), sizeof(double) * host.size());
-        sh.desc_off = hoff;
-        sh.image_off = doff;
-        sh.state = XRT_SHOT_RUNNING;
+        std::memcpy(s->host_arena + w.host_off, &d, sizeof d);
+        std::memcpy(s->host_arena + w.host_off + d.mats_rel, host.data(), sizeof(double) * host.size());
         sh.t_admit = s->now();
-        sh.n_tiles = d.p.n_tiles;
-        sh.terms_per_pixel = (uint64_t)d.p.O * (uint64_t)d.p.O * (uint64_t)d.p.T * (uint64_t)d.p.n_src *
-                             (uint64_t)d.p.n_rot;
-        start_phase(s, sh, xrt::CHUNK_COMPUTE);
-        sh.work_published = s->vtime;  // it competes from now on, not from the start
-        s->resident++;
-        s->admitted.push_back(sh.ticket);
-        s->queue.pop_front();
-    }
-    return XRT_OK;
+        return XRT_OK;
+    });
 }
 
-// (3) publication, while fewer than two chunks per workgroup are in flight:
-// the next chunk always comes from the admitted shot with the least work
-// published so far (pixel-terms; ties to the earlier ticket), so resident
-// shots share the device evenly by work whatever their chunk sizes, and a
-// small shot admitted later is not stuck behind a large one.  The shallow
-// queue lets a newly admitted shot's chunks enter the ring as soon as earlier
-// chunks finish.
+// (3) publication (the scheduler's order and depth) into the ring, then the
+// tail moves (release): the kernel may claim the new chunks from then on.
 void publish(xrt_server *s)
 {
-    const size_t depth = std::min<size_t>(RING - 1, 2 * (size_t)s->n_wg);
-    bool any = false;
-    while (s->inflight.size() < depth && !s->admitted.empty()) {
-        size_t best = 0;
-        for (size_t i = 1; i < s->admitted.size(); ++i) {
-            const Shot &a = s->shots[s->admitted[i]], &b = s->shots[s->admitted[best]];
-            if (a.work_published < b.work_published ||
-                (a.work_published == b.work_published && a.ticket < b.ticket))
-                best = i;
-        }
-        Shot &sh = s->shots[s->admitted[best]];
-        s->vtime = sh.work_published;
-        const uint64_t seq = s->tail;
-        xrt::ServeChunk &c = s->ring[seq % RING];
-        c.desc_off = sh.desc_off;
-        c.tile0 = sh.next_unit;
-        c.n_tiles = std::min(sh.chunk_units, sh.n_units - sh.next_unit);
-        c.seq1 = (uint32_t)(seq + 1);
-        c.shot = (uint32_t)sh.ticket ? (uint32_t)sh.ticket : 1u;
-        c.kind = sh.phase;
+    const size_t n = s->sched->publish([s](const xrt::sched::Chunk &k, const xrt::sched::Work &w) {
+        xrt::ServeChunk &c = s->ring[k.seq % RING];
+        c.desc_off = w.host_off;
+        c.tile0 = k.unit0;
+        c.n_tiles = k.n_units;
+        c.seq1 = (uint32_t)(k.seq + 1);
+        c.shot = (uint32_t)w.ticket ? (uint32_t)w.ticket : 1u;
+        c.kind = k.kind;
         c.pad = 0;
-        sh.next_unit += c.n_tiles;
-        // a reduce chunk reads K values per pixel: count it as K terms
-        sh.work_published += (double)c.n_tiles * TILE_PIXELS *
-                             (sh.phase == xrt::CHUNK_COMPUTE ? (double)sh.terms_per_pixel / sh.split : sh.split);
-        s->inflight.push_back({seq, sh.ticket});
-        s->tail++;
-        any = true;
-        if (sh.next_unit >= sh.n_units) s->admitted.erase(s->admitted.begin() + best);
-    }
-    if (any) __atomic_store_n(&s->ctrl->tail, s->tail, __ATOMIC_RELEASE);
+    });
+    if (n) __atomic_store_n(&s->ctrl->tail, s->sched->published(), __ATOMIC_RELEASE);
 }
 
 xrt_status launch(xrt_server *s)
@@ -347,7 +206,7 @@ xrt_status launch(xrt_server *s)
     hipError_t err;
     const bool running = kernel_running(s, &err);
     if (err != hipSuccess) return hip_fail(err, "xrt_server_progress: persistent kernel");
-    if (s->inflight.empty() || running) return XRT_OK;
+    if (s->sched->in_flight() == 0 || running) return XRT_OK;
     xrt::ServeArgs a{};
     a.ctrl = s->ctrl;
     a.ring = s->ring;
@@ -415,9 +274,8 @@ xrt_status xrt_server_create(const xrt_server_desc *desc, const xrt_fhkl *fhkl, 
     std::memset(s->ctrl, 0, sizeof(xrt::ServeCtrl));
     std::memset(s->ring, 0, sizeof(xrt::ServeChunk) * RING);
     std::memset(s->done, 0, sizeof(uint32_t) * RING);
-    s->arena = new (std::nothrow) Arena(desc->hbm_budget);
-    s->harena = new (std::nothrow) Arena(s->host_bytes);
-    if (!s->arena || !s->harena) {
+    s->sched = new (std::nothrow) xrt::sched::Scheduler(desc->hbm_budget, s->host_bytes, desc->max_resident, s->n_wg, RING);
+    if (!s->sched) {
         free_server(s);
         return fail(XRT_ENOMEM, "host allocation failed");
     }
@@ -459,25 +317,27 @@ xrt_status xrt_server_submit(xrt_server *s, const xrt_detector *det, const xrt_b
     sh.lam.assign(beam->lambda, beam->lambda + beam->n_src);
     sh.weight.assign(beam->weight, beam->weight + beam->n_src);
     sh.umats.assign(xtal->umats, xtal->umats + 9 * (size_t)xtal->n_mos);
+    xrt::sched::Work w;
     const uint64_t n_pix = (uint64_t)(det->roi_f1 - det->roi_f0) * (uint64_t)(det->roi_s1 - det->roi_s0);
     const uint64_t tables = sizeof(double) * (9 * (uint64_t)xtal->n_phi * xtal->n_mos + xrt::SRC_STRIDE * (uint64_t)beam->n_src);
-    sh.desc_bytes = align_up(align_up(sizeof(xrt::ShotDesc)) + tables);
+    w.desc_bytes = align_up(align_up(sizeof(xrt::ShotDesc)) + tables);
     sh.image_bytes = n_pix * (s->desc.out_dtype == XRT_F64 ? 8 : 4);
     // split sums keep their part sums in the arena after the image
-    sh.split = xrt::host::split_of(det, beam, xtal);
-    const uint64_t n_tiles = (uint64_t)((det->roi_f1 - det->roi_f0 + 15) / 16) *
-                             (uint64_t)((det->roi_s1 - det->roi_s0 + 15) / 16);
-    sh.part_bytes = sh.split > 1 ? sizeof(double) * n_tiles * (uint64_t)sh.split * TILE_PIXELS : 0;
-    sh.footprint = align_up(sh.image_bytes) + align_up(sh.part_bytes);
-    if (sh.footprint > s->desc.hbm_budget)
+    w.split = xrt::host::split_of(det, beam, xtal);
+    w.n_tiles = (int32_t)(((det->roi_f1 - det->roi_f0 + 15) / 16) * ((det->roi_s1 - det->roi_s0 + 15) / 16));
+    w.terms_per_pixel = (uint64_t)det->oversample * det->oversample * det->n_layers * (uint64_t)beam->n_src *
+                        (uint64_t)xtal->n_phi * xtal->n_mos;
+    sh.part_bytes = w.split > 1 ? sizeof(double) * (uint64_t)w.n_tiles * (uint64_t)w.split * xrt::sched::TILE_PIXELS : 0;
+    w.footprint = align_up(sh.image_bytes) + align_up(sh.part_bytes);
+    if (w.footprint > s->desc.hbm_budget)
         return fail(XRT_ERANGE, "shot needs %llu bytes, more than the server's budget %llu",
-                    (unsigned long long)sh.footprint, (unsigned long long)s->desc.hbm_budget);
+                    (unsigned long long)w.footprint, (unsigned long long)s->desc.hbm_budget);
     std::lock_guard<std::mutex> g(s->mu);
-    sh.ticket = s->next_ticket++;
+    w.ticket = s->next_ticket++;
     sh.t_submit = s->now();
-    *ticket = sh.ticket;
-    s->queue.push_back(sh.ticket);
-    s->shots.emplace(sh.ticket, std::move(sh));
+    *ticket = w.ticket;
+    s->shots.emplace(w.ticket, std::move(sh));
+    s->sched->submit(w);
     return XRT_OK;
 }
 
@@ -508,7 +368,8 @@ xrt_status xrt_server_info(xrt_server *s, uint64_t ticket, xrt_shot_info *info)
     auto it = s->shots.find(ticket);
     if (it == s->shots.end()) return fail(XRT_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
     const Shot &sh = it->second;
-    info->state = sh.state;
+    const xrt::sched::Work *w = s->sched->find(ticket);
+    info->state = w ? w->state : XRT_SHOT_DONE;
     info->image_bytes = sh.image_bytes;
     info->roi_nf = sh.det.roi_f1 - sh.det.roi_f0;
     info->roi_ns = sh.det.roi_s1 - sh.det.roi_s0;
@@ -522,10 +383,10 @@ xrt_status xrt_server_image(xrt_server *s, uint64_t ticket, const void **dev_ima
 {
     if (!s || !dev_image) return fail(XRT_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> g(s->mu);
-    auto it = s->shots.find(ticket);
-    if (it == s->shots.end()) return fail(XRT_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
-    if (it->second.state != XRT_SHOT_DONE) return fail(XRT_EBUSY, "shot %llu is not done", (unsigned long long)ticket);
-    *dev_image = s->dev_arena + it->second.image_off;
+    const xrt::sched::Work *w = s->sched->find(ticket);
+    if (!w) return fail(XRT_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    if (w->state != xrt::sched::DONE) return fail(XRT_EBUSY, "shot %llu is not done", (unsigned long long)ticket);
+    *dev_image = s->dev_arena + w->dev_off;
     return XRT_OK;
 }
 
@@ -533,13 +394,11 @@ xrt_status xrt_server_release(xrt_server *s, uint64_t ticket)
 {
     if (!s) return fail(XRT_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> g(s->mu);
-    auto it = s->shots.find(ticket);
-    if (it == s->shots.end()) return fail(XRT_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
-    if (it->second.state != XRT_SHOT_DONE) return fail(XRT_EBUSY, "shot %llu is not done", (unsigned long long)ticket);
-    s->arena->release(it->second.image_off, it->second.footprint);
-    s->harena->release(it->second.desc_off, it->second.desc_bytes);
-    s->resident--;
-    s->shots.erase(it);
+    const xrt::sched::Work *w = s->sched->find(ticket);
+    if (!w) return fail(XRT_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    if (w->state != xrt::sched::DONE) return fail(XRT_EBUSY, "shot %llu is not done", (unsigned long long)ticket);
+    s->sched->release(ticket);
+    s->shots.erase(ticket);
     return XRT_OK;
 }
 

@@ -1,0 +1,283 @@
+// CPU checks of the shot server's scheduling logic (paper_2205_07976_amd/
+// csrc/xrt_sched.h) against a simulated device: chunks are "run" by marking
+// them done, in publication order or scrambled.  Each check prints its name;
+// the first failure prints the condition and exits with status 1.
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <map>
+#include <random>
+#include <set>
+#include <vector>
+
+#include "../paper_2205_07976_amd/csrc/xrt_sched.h"
+
+using namespace xrt::sched;
+
+#define CHECK(c)                                                                  \
+    do {                                                                          \
+        if (!(c)) {                                                               \
+            fprintf(stderr, "%s:%d: check failed: %s\n", __FILE__, __LINE__, #c); \
+            exit(1);                                                              \
+        }                                                                         \
+    } while (0)
+
+static Work shot(uint64_t ticket, uint64_t footprint, int32_t n_tiles, uint64_t tpp, int32_t split = 1,
+                 uint64_t desc = 4096)
+{
+    Work w;
+    w.ticket = ticket;
+    w.footprint = footprint;
+    w.desc_bytes = desc;
+    w.n_tiles = n_tiles;
+    w.terms_per_pixel = tpp;
+    w.split = split;
+    return w;
+}
+
+// A simulated device: published chunks wait in `pending`; run(n) finishes n
+// of them (the oldest, or random ones), collect() hands the finished ones to
+// the scheduler.
+struct Device {
+    Scheduler &s;
+    std::vector<Chunk> pending;
+    std::set<uint64_t> done;
+    std::vector<Chunk> log;  // every chunk ever published
+    std::mt19937_64 rng{7};
+    explicit Device(Scheduler &sc) : s(sc) {}
+    size_t publish()
+    {
+        return s.publish([&](const Chunk &c, const Work &) {
+            // a reduce chunk comes only after every compute chunk of its shot is done
+            if (c.kind == PHASE_REDUCE)
+                for (const Chunk &x : log)
+                    if (x.ticket == c.ticket && x.kind == PHASE_COMPUTE) CHECK(done.count(x.seq));
+            pending.push_back(c);
+            log.push_back(c);
+        });
+    }
+    void run(size_t n, bool scrambled)
+    {
+        for (size_t i = 0; i < n && !pending.empty(); ++i) {
+            size_t k = scrambled ? rng() % pending.size() : 0;
+            done.insert(pending[k].seq);
+            pending.erase(pending.begin() + k);
+        }
+    }
+    std::vector<uint64_t> collect()
+    {
+        std::vector<uint64_t> fin;
+        s.collect([&](uint64_t seq) { return done.count(seq) > 0; }, &fin);
+        return fin;
+    }
+};
+
+static void check_arena()
+{
+    printf("arena: first fit, coalescing, no overlap under random use\n");
+    Arena a(1000);
+    uint64_t o1, o2, o3, o4;
+    CHECK(a.alloc(100, &o1) && o1 == 0);
+    CHECK(a.alloc(200, &o2) && o2 == 100);
+    CHECK(a.alloc(300, &o3) && o3 == 300);
+    CHECK(!a.alloc(401, &o4));
+    a.release(o2, 200);
+    CHECK(a.alloc(150, &o4) && o4 == 100);  // first fit reuses the hole
+    a.release(o4, 150);
+    a.release(o1, 100);
+    a.release(o3, 300);
+    CHECK(a.free_blocks().size() == 1 && a.free_blocks().begin()->second == 1000);
+    std::mt19937_64 rng(3);
+    std::map<uint64_t, uint64_t> live;  // offset -> length
+    Arena b(1 << 20);
+    for (int it = 0; it < 20000; ++it) {
+        if (!live.empty() && (rng() % 3 == 0 || live.size() > 200)) {
+            auto p = live.begin();
+            std::advance(p, rng() % live.size());
+            b.release(p->first, p->second);
+            live.erase(p);
+        } else {
+            uint64_t n = 1 + rng() % 20000, off;
+            if (b.alloc(n, &off)) {
+                CHECK(off + n <= b.size());
+                auto nx = live.lower_bound(off);
+                CHECK(nx == live.end() || off + n <= nx->first);
+                if (nx != live.begin()) {
+                    auto pv = std::prev(nx);
+                    CHECK(pv->first + pv->second <= off);
+                }
+                live[off] = n;
+            }
+        }
+        // free + live = everything, free blocks disjoint and coalesced
+        uint64_t total = 0, end = 0;
+        bool first = true;
+        for (auto &f : b.free_blocks()) {
+            CHECK(first || f.first > end);  // strictly after the previous block: coalesced
+            total += f.second;
+            end = f.first + f.second;
+            first = false;
+        }
+        for (auto &l : live) total += l.second;
+        CHECK(total == b.size());
+    }
+}
+
+static void check_fifo_admission()
+{
+    printf("admission: arrival order, no overtaking, HBM budget and slots\n");
+    Scheduler s(1000, 1 << 20, 3, 4, 1 << 16);
+    Device d(s);
+    s.submit(shot(1, 600, 4, 1000));
+    s.submit(shot(2, 600, 4, 1000));  // does not fit beside 1
+    s.submit(shot(3, 100, 4, 1000));  // would fit, but must not overtake 2
+    CHECK(s.admit([](Work &) { return 0; }) == 0);
+    CHECK(s.find(1)->state == RUNNING && s.find(2)->state == QUEUED && s.find(3)->state == QUEUED);
+    // run shot 1 to completion
+    for (int i = 0; i < 100 && s.find(1)->state != DONE; ++i) {
+        d.publish();
+        d.run(100, false);
+        d.collect();
+    }
+    CHECK(s.find(1)->state == DONE);
+    s.admit([](Work &) { return 0; });
+    CHECK(s.find(2)->state == QUEUED);  // memory of 1 not yet released
+    CHECK(s.release(1));
+    s.admit([](Work &) { return 0; });
+    CHECK(s.find(2)->state == RUNNING && s.find(3)->state == RUNNING);
+    // the resident-slot limit
+    Scheduler t(1 << 30, 1 << 20, 2, 4, 1 << 16);
+    for (uint64_t k = 1; k <= 5; ++k) t.submit(shot(k, 100, 4, 1000));
+    t.admit([](Work &) { return 0; });
+    CHECK(t.resident() == 2 && t.find(3)->state == QUEUED);
+    // a failing preparation frees the space and stops admission
+    Scheduler u(1000, 1 << 20, 8, 4, 1 << 16);
+    u.submit(shot(1, 500, 4, 1000));
+    u.submit(shot(2, 500, 4, 1000));
+    CHECK(u.admit([](Work &w) { return w.ticket == 1 ? -7 : 0; }) == -7);
+    CHECK(u.find(1)->state == QUEUED && u.resident() == 0);
+    CHECK(u.dev_arena().free_blocks().begin()->second == 1000);
+}
+
+static void check_units_and_depth()
+{
+    printf("chunks: every unit of every phase exactly once, depth bound, split phases in order\n");
+    Scheduler s(1 << 30, 1 << 22, 64, 16, 1 << 16);
+    Device d(s);
+    std::map<uint64_t, Work> shots;
+    std::mt19937_64 rng(11);
+    for (uint64_t k = 1; k <= 40; ++k) {
+        const int32_t tiles = 1 + (int32_t)(rng() % 300);
+        const uint64_t tpp = 1 + rng() % 200000;
+        const int32_t split = (rng() % 3 == 0) ? 1 + (int32_t)(rng() % 64) : 1;
+        shots[k] = shot(k, 4096, tiles, tpp, split);
+        s.submit(shots[k]);
+    }
+    std::map<uint64_t, int> finished;
+    for (int it = 0; it < 100000 && finished.size() < shots.size(); ++it) {
+        s.admit([](Work &) { return 0; });
+        d.publish();
+        CHECK(s.in_flight() <= s.depth() && s.depth() == 32);
+        d.run(1 + rng() % 40, true);
+        for (uint64_t t : d.collect()) finished[t]++;
+    }
+    CHECK(finished.size() == shots.size());
+    for (auto &f : finished) CHECK(f.second == 1);
+    // coverage per (shot, phase)
+    std::map<std::pair<uint64_t, int>, std::vector<int>> cover;
+    std::map<uint64_t, uint64_t> last_compute, first_reduce;
+    for (const Chunk &c : d.log) {
+        auto &v = cover[{c.ticket, c.kind}];
+        const Work &w = shots[c.ticket];
+        const int n = c.kind == PHASE_COMPUTE ? w.n_tiles * w.split : w.n_tiles;
+        if (v.empty()) v.assign(n, 0);
+        CHECK(c.n_units >= 1 && c.n_units <= MAX_CHUNK && c.unit0 >= 0 && c.unit0 + c.n_units <= n);
+        for (int u = c.unit0; u < c.unit0 + c.n_units; ++u) v[u]++;
+        if (c.kind == PHASE_COMPUTE) last_compute[c.ticket] = std::max(last_compute[c.ticket], c.seq);
+        if (c.kind == PHASE_REDUCE && !first_reduce.count(c.ticket)) first_reduce[c.ticket] = c.seq;
+    }
+    for (auto &kv : shots) {
+        const Work &w = kv.second;
+        for (int x : cover[{w.ticket, PHASE_COMPUTE}]) CHECK(x == 1);
+        if (w.split > 1) {
+            CHECK(cover.count({w.ticket, PHASE_REDUCE}));
+            for (int x : cover[{w.ticket, PHASE_REDUCE}]) CHECK(x == 1);
+            CHECK(first_reduce[w.ticket] > last_compute[w.ticket]);
+        } else {
+            CHECK(!cover.count({w.ticket, PHASE_REDUCE}));
+        }
+    }
+    for (auto &kv : shots) CHECK(s.release(kv.first));
+    CHECK(s.dev_arena().free_blocks().size() == 1 && s.resident() == 0);
+}
+
+static void check_fair_share()
+{
+    printf("publication: backlogged shots share by work, a late shot joins at the current level\n");
+    // shot 1: cheap units (tpp 1000: 64 tiles per chunk); shot 2: costly
+    // units (tpp 100000: 1 tile per chunk)
+    Scheduler s(1 << 30, 1 << 22, 8, 4, 1 << 16);
+    Device d(s);
+    s.submit(shot(1, 4096, 100000, 1000));
+    s.submit(shot(2, 4096, 100000, 100000));
+    s.admit([](Work &) { return 0; });
+    double max_chunk = 0;
+    for (int it = 0; it < 2000; ++it) {
+        d.publish();
+        d.run(8, false);
+        d.collect();
+        const double a = s.find(1)->work_published, b = s.find(2)->work_published;
+        max_chunk = std::max(max_chunk, 256.0 * 100000);
+        CHECK(std::abs(a - b) <= max_chunk + 1);  // within one chunk of each other
+    }
+    // a third shot arriving now starts at the current level: it does not get
+    // the device alone until it catches up with the others
+    s.submit(shot(3, 4096, 100000, 100000));
+    s.admit([](Work &) { return 0; });
+    const double w1 = s.find(1)->work_published, w2 = s.find(2)->work_published;
+    CHECK(s.find(3)->work_published >= std::min(w1, w2) - max_chunk);
+    CHECK(s.find(3)->work_published <= std::max(w1, w2));
+    size_t n1 = 0, n2 = 0, n3 = 0;
+    const size_t mark = d.log.size();
+    for (int it = 0; it < 600; ++it) {
+        d.publish();
+        d.run(8, false);
+        d.collect();
+    }
+    for (size_t i = mark; i < d.log.size(); ++i) {
+        const Chunk &c = d.log[i];
+        (c.ticket == 1 ? n1 : c.ticket == 2 ? n2 : n3) += 1;
+    }
+    CHECK(n2 > 0 && n3 > 0 && n1 > 0);
+    CHECK(n2 * 10 >= n3 * 8 && n3 * 10 >= n2 * 8);  // equal-cost chunks: equal counts, within 20 %
+}
+
+static void check_ring_sequence()
+{
+    printf("ring: sequence numbers increase by one across many wraps\n");
+    Scheduler s(1 << 30, 1 << 22, 4, 2, 16);  // tiny ring: depth min(15, 4)
+    Device d(s);
+    s.submit(shot(1, 4096, 20000, 10));
+    s.admit([](Work &) { return 0; });
+    CHECK(s.depth() == 4);
+    for (int it = 0; it < 10000 && s.find(1)->state != DONE; ++it) {
+        d.publish();
+        CHECK(s.in_flight() <= 4);
+        d.run(3, true);
+        d.collect();
+    }
+    CHECK(s.find(1)->state == DONE);
+    for (size_t i = 0; i < d.log.size(); ++i) CHECK(d.log[i].seq == i);
+    CHECK(d.log.size() > 16 * 10);
+}
+
+int main()
+{
+    check_arena();
+    check_fifo_admission();
+    check_units_and_depth();
+    check_fair_share();
+    check_ring_sequence();
+    printf("all scheduler checks passed\n");
+    return 0;
+}
