@@ -307,6 +307,13 @@ xrt_status xrt_server_release(xrt_server *srv, uint64_t ticket);
  * Errors: ERANGE (n < 0), EINVAL (NULL arrays), EDEVICE. */
 xrt_status xrt_sinpi(const double *dev_x, int64_t n, double *dev_s64, float *dev_s32, hipStream_t stream);
 
+/* Diagnostics: the binary64 kernels' exp(x) (the Gaussian lattice factor,
+ * section II's crystal-size transform in its Gaussian form): reduction by
+ * x = n ln2 + r, a polynomial for exp(r), scaling by 2^n; for x <= 709.
+ * dev_x, dev_y: [n] binary64.  Enqueued on `stream`.
+ * Errors: ERANGE (n < 0), EINVAL (NULL arrays), EDEVICE. */
+xrt_status xrt_exp(const double *dev_x, int64_t n, double *dev_y, hipStream_t stream);
+
 /* Diagnostics: the library's lab-frame cell matrices M_{k,m} (host output,
  * [n_phi*n_mos][3][3], rows a', b', c'), exactly as the kernels receive them. */
 xrt_status xrt_cell_mats(const xrt_crystal *xtal, double *host_out);

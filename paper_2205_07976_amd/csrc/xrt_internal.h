@@ -150,6 +150,7 @@ hipError_t launch_grad(const Params &p, int precision, bool clamp, const void *d
                        double *partial, double *grad13, double inv_scale, hipStream_t stream);
 hipError_t launch_serve(const ServeArgs &a, int precision, int shape, int n_wg, hipStream_t stream);
 hipError_t launch_sinpi(const double *x, int64_t n, double *s64, float *s32, hipStream_t stream);
+hipError_t launch_exp(const double *x, int64_t n, double *y, hipStream_t stream);
 hipError_t launch_trace(const Params &p, int64_t n, const int32_t *idx, double *S, double *h,
                         hipStream_t stream);
 

@@ -171,7 +171,7 @@ __device__ __forceinline__ double term_f64(const Params &p, __amdgpu_buffer_rsrc
             const double f = h[i] - hr[i];
             e = __builtin_fma(-p.gk[i], f * f, e);
         }
-        L2 = exp(e);
+        L2 = exp_f64(e);
     }
     return load_f64(tab, table_offset<CLAMP>(p, hr, p.sa8, p.sb8, 8.0, p.off8)) * L2;
 }
@@ -709,7 +709,7 @@ __device__ __forceinline__ void grad_term_f64(const Params &p, __amdgpu_buffer_r
         f[i] = h - hr[i];
         e = __builtin_fma(-p.gk[i], f[i] * f[i], e);
     }
-    const double base = w * load_f64(tab, table_offset<CLAMP>(p, hr, p.sa8, p.sb8, 8.0, p.off8)) * exp(e);
+    const double base = w * load_f64(tab, table_offset<CLAMP>(p, hr, p.sa8, p.sb8, 8.0, p.off8)) * exp_f64(e);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const double dh = base * p.m2gk[i] * f[i];
@@ -911,6 +911,19 @@ hipError_t launch_sinpi(const double *x, int64_t n, double *s64, float *s32, hip
 {
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(sinpi_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, x, n, s64, s32);
+    return hipGetLastError();
+}
+
+__global__ void exp_kernel(const double *x, int64_t n, double *y)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q < n) y[q] = exp_f64(x[q]);
+}
+
+hipError_t launch_exp(const double *x, int64_t n, double *y, hipStream_t stream)
+{
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(exp_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, x, n, y);
     return hipGetLastError();
 }
 

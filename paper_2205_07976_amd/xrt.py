@@ -96,7 +96,7 @@ _lib = None
 SYMBOLS = ("xrt_version", "xrt_last_error", "xrt_fhkl_create", "xrt_fhkl_destroy",
            "xrt_simulate", "xrt_simulate_rois", "xrt_backward_rois", "xrt_server_create",
            "xrt_server_destroy", "xrt_server_submit", "xrt_server_progress", "xrt_server_info",
-           "xrt_server_image", "xrt_server_release", "xrt_cell_mats", "xrt_trace_terms", "xrt_sinpi")
+           "xrt_server_image", "xrt_server_release", "xrt_cell_mats", "xrt_trace_terms", "xrt_sinpi", "xrt_exp")
 XRT_SHOT_QUEUED, XRT_SHOT_RUNNING, XRT_SHOT_DONE = 0, 1, 2
 
 
@@ -132,6 +132,7 @@ def load():
     lib.xrt_trace_terms.argtypes = [C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal), C.c_int64,
                                     C.c_void_p, C.c_void_p, C.c_void_p]
     lib.xrt_sinpi.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.xrt_exp.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
     for name in SYMBOLS:
         if name != "xrt_last_error":
             getattr(lib, name).restype = C.c_int32
@@ -325,6 +326,17 @@ def sinpi(x, stream=None):
     _check(load().xrt_sinpi(C.c_void_p(x.data_ptr()), x.numel(), C.c_void_p(s64.data_ptr()),
                             C.c_void_p(s32.data_ptr()), _stream(stream)))
     return s64, s32
+
+
+def exp(x, stream=None):
+    """The binary64 kernels' exp of a binary64 CUDA tensor."""
+    import torch
+    if not (x.is_cuda and x.dtype == torch.float64):
+        raise ValueError("x must be a binary64 tensor on the GPU")
+    x = x.contiguous()
+    y = torch.empty_like(x)
+    _check(load().xrt_exp(C.c_void_p(x.data_ptr()), x.numel(), C.c_void_p(y.data_ptr()), _stream(stream)))
+    return y
 
 
 class Server:

@@ -137,3 +137,11 @@ def test_sinpi_validation():
     assert lib.xrt_sinpi(None, 4, C.c_void_p(8), None, None) == xrt.XRT_EINVAL
     assert lib.xrt_sinpi(C.c_void_p(8), 4, None, None, None) == xrt.XRT_EINVAL
     assert lib.xrt_sinpi(None, 0, None, None, None) == xrt.XRT_OK  # nothing to do, nothing launched
+
+
+def test_exp_validation():
+    lib = xrt.load()
+    assert lib.xrt_exp(C.c_void_p(8), -1, C.c_void_p(8), None) == xrt.XRT_ERANGE
+    assert lib.xrt_exp(None, 4, C.c_void_p(8), None) == xrt.XRT_EINVAL
+    assert lib.xrt_exp(C.c_void_p(8), 4, None, None) == xrt.XRT_EINVAL
+    assert lib.xrt_exp(None, 0, None, None) == xrt.XRT_OK

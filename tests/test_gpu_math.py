@@ -80,3 +80,30 @@ def test_sinpi_binary32_exhaustive():
             worst, where = m, float(x[int(u.argmax())])
     say("binary32 sinpi: max", worst, "ulp at x =", where, f"({top + 1 - first} inputs)")
     assert worst <= 3.0
+
+
+def test_exp_binary64_against_extended_precision():
+    """The binary64 kernels' exp (Gaussian lattice factor) against 80-bit host
+    exp on 2^21 seeded points of [-760, 45] (the lattice exponents lie in
+    (-inf, log(Na^2 Nb^2 Nc^2)]), including the subnormal range and exact 0
+    below it.  Bound: 2 ulp (fit 0.2 ulp + Horner and reduction roundings);
+    a subnormal result is that value rounded once more to the subnormal grid:
+    2 ulp of the unrounded value (at most 2 spacings) + half a spacing."""
+    assert np.finfo(np.longdouble).nmant >= 63, "needs 80-bit long double on the host"
+    rng = np.random.default_rng(12)
+    x = np.concatenate([rng.uniform(-760.0, 45.0, 1 << 21), rng.uniform(-2.0, 2.0, 1 << 16),
+                        np.array([0.0, -0.0, 1e-300, -745.2, -745.1, -708.4, -708.3, 41.4, -1e4, -1e6])])
+    y = xrt.exp(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = np.exp(x.astype(np.longdouble))
+    ref64 = ref.astype(np.float64)
+    assert np.all(y[ref64 == 0] == 0)  # below the binary64 range: exactly 0
+    nz = ref64 != 0
+    err = np.abs(y[nz].astype(np.longdouble) - ref[nz])
+    spacing = np.spacing(ref64[nz]).astype(np.longdouble)
+    ulps = (err / spacing).astype(np.float64)
+    normal = ref64[nz] >= np.finfo(np.float64).tiny
+    say("binary64 exp: max", ulps[normal].max(), "ulp (normal results), max", ulps[~normal].max() if (~normal).any()
+        else 0.0, "spacing (subnormal results)")
+    assert ulps[normal].max() <= 2.0
+    assert (~normal).sum() > 0 and ulps[~normal].max() <= 2.5
+    assert y[x == 0.0][0] == 1.0
