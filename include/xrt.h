@@ -226,14 +226,16 @@ xrt_status xrt_backward_rois(const xrt_detector *det, const xrt_beam *beam,
  *
  * The paper runs many simulations per GPU and lets several producers share a
  * GPU to hide latency (section IV, ranks per GPU).  A server owns one arena of
- * device memory (its HBM budget, holding the images) and the structure
+ * device memory (its HBM budget, holding the images and, for shots whose
+ * per-pixel sums are split, their part sums) and borrows the structure
  * factors (shared by every shot); shot descriptors and tables sit in pinned
  * host memory that the kernel reads directly.  Submitted shots wait in
- * arrival order; a shot is admitted when its image fits in the arena and a
- * resident slot is free; the tiles of admitted shots are fed, round-robin in
- * chunks, to a persistent kernel that keeps running while new shots join.  Every pixel is
- * computed exactly as by xrt_simulate with the server's precision, so a shot's
- * image is bit-identical whatever else runs beside it.
+ * arrival order; a shot is admitted when its footprint fits in the arena and
+ * a resident slot is free; the work of admitted shots is fed in chunks, the
+ * shot with the least work published so far first, to a persistent kernel
+ * that keeps running while new shots join.  Every pixel is computed exactly
+ * as by xrt_simulate with the server's precision (the same summation order),
+ * so a shot's image is bit-identical whatever else runs beside it.
  * Calls on one server are serialised internally; progress is driven by
  * xrt_server_progress (call it often: it admits, publishes, launches and
  * collects).  Limits per served shot: n_phi*n_mos <= 256, n_src <= 128.
@@ -284,8 +286,10 @@ xrt_status xrt_server_submit(xrt_server *srv, const xrt_detector *det,
                              const xrt_beam *beam, const xrt_crystal *xtal,
                              uint64_t *ticket);
 
-/* Admit, upload, publish, launch and collect; *n_done receives the number of
- * shots seen finishing during this call (may be NULL). */
+/* Collect finished work, admit queued shots, publish chunks and (re)launch the
+ * persistent kernel if it is not running; *n_done receives the number of
+ * shots seen finishing during this call (may be NULL).  Errors: EINVAL (wrong
+ * device), EDEVICE (the kernel or a launch failed). */
 xrt_status xrt_server_progress(xrt_server *srv, int32_t *n_done);
 
 /* State and times of a shot.  info->struct_size must be set. */
@@ -305,14 +309,14 @@ xrt_status xrt_server_release(xrt_server *srv, uint64_t ticket);
  * dev_x: [n] binary64; outputs [n]; either output may be NULL, not both.
  * Enqueued on `stream`; outside [-1/2, 1/2] the value is the polynomial's.
  * Errors: ERANGE (n < 0), EINVAL (NULL arrays), EDEVICE. */
-xrt_status xrt_sinpi(const double *dev_x, int64_t n, double *dev_s64, float *dev_s32, hipStream_t stream);
+xrt_status xrt_sinpi(const double *dev_x, int64_t n, double *dev_s64, float *dev_s32, void *stream);
 
 /* Diagnostics: the binary64 kernels' exp(x) (the Gaussian lattice factor,
  * section II's crystal-size transform in its Gaussian form): reduction by
  * x = n ln2 + r, a polynomial for exp(r), scaling by 2^n; for x <= 709.
  * dev_x, dev_y: [n] binary64.  Enqueued on `stream`.
  * Errors: ERANGE (n < 0), EINVAL (NULL arrays), EDEVICE. */
-xrt_status xrt_exp(const double *dev_x, int64_t n, double *dev_y, hipStream_t stream);
+xrt_status xrt_exp(const double *dev_x, int64_t n, double *dev_y, void *stream);
 
 /* Diagnostics: the library's lab-frame cell matrices M_{k,m} (host output,
  * [n_phi*n_mos][3][3], rows a', b', c'), exactly as the kernels receive them. */

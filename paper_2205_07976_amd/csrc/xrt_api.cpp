@@ -714,22 +714,22 @@ xrt_status xrt_trace_terms(const xrt_detector *det, const xrt_beam *beam, const 
     return XRT_OK;
 }
 
-xrt_status xrt_exp(const double *dev_x, int64_t n, double *dev_y, hipStream_t stream)
+xrt_status xrt_exp(const double *dev_x, int64_t n, double *dev_y, void *stream)
 {
     if (n < 0 || n > ((int64_t)1 << 40)) return fail(XRT_ERANGE, "n must be in [0, 2^40]");
     if (n == 0) return XRT_OK;
     if (!dev_x || !dev_y) return fail(XRT_EINVAL, "NULL array");
-    const hipError_t e = xrt::launch_exp(dev_x, n, dev_y, stream);
+    const hipError_t e = xrt::launch_exp(dev_x, n, dev_y, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "xrt_exp");
     return XRT_OK;
 }
 
-xrt_status xrt_sinpi(const double *dev_x, int64_t n, double *dev_s64, float *dev_s32, hipStream_t stream)
+xrt_status xrt_sinpi(const double *dev_x, int64_t n, double *dev_s64, float *dev_s32, void *stream)
 {
     if (n < 0 || n > ((int64_t)1 << 40)) return fail(XRT_ERANGE, "n must be in [0, 2^40]");
     if (n == 0) return XRT_OK;
     if (!dev_x || (!dev_s64 && !dev_s32)) return fail(XRT_EINVAL, "NULL array");
-    const hipError_t e = xrt::launch_sinpi(dev_x, n, dev_s64, dev_s32, stream);
+    const hipError_t e = xrt::launch_sinpi(dev_x, n, dev_s64, dev_s32, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "xrt_sinpi");
     return XRT_OK;
 }

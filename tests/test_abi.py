@@ -145,3 +145,18 @@ def test_exp_validation():
     assert lib.xrt_exp(None, 4, C.c_void_p(8), None) == xrt.XRT_EINVAL
     assert lib.xrt_exp(C.c_void_p(8), 4, None, None) == xrt.XRT_EINVAL
     assert lib.xrt_exp(None, 0, None, None) == xrt.XRT_OK
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/xrt.h compiles as strict C99 on its own: no HIP, C++ or torch
+    types leak into the boundary."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "use.c"
+    src.write_text('#include "include/xrt.h"\nint main(void) { xrt_detector d; (void)d; return XRT_OK; }\n')
+    subprocess.run([cc, "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror", "-I", root, "-c", str(src),
+                    "-o", str(tmp_path / "use.o")], check=True)
