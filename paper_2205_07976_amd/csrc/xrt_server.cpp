@@ -85,7 +85,7 @@ struct xrt_server {
     xrt::ServeCtrl *ctrl = nullptr;
     xrt::ServeChunk *ring = nullptr;
     uint32_t *done = nullptr;
-    hipStream_t work = nullptr, copy = nullptr;
+    hipStream_t work = nullptr;              // the persistent kernel's stream
     hipEvent_t kernel_done = nullptr;
     bool launched = false;
     int n_wg = 0;
@@ -119,7 +119,6 @@ void free_server(xrt_server *s)
 {
     if (s->kernel_done) (void)hipEventDestroy(s->kernel_done);
     if (s->work) (void)hipStreamDestroy(s->work);
-    if (s->copy) (void)hipStreamDestroy(s->copy);
     if (s->dev_arena) (void)hipFree(s->dev_arena);
     if (s->dev_ctl) (void)hipFree(s->dev_ctl);
     if (s->ctrl) (void)hipHostFree(s->ctrl);
@@ -264,7 +263,6 @@ xrt_status xrt_server_create(const xrt_server_desc *desc, const xrt_fhkl *fhkl, 
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->done, sizeof(uint32_t) * RING, hipHostMallocCoherent);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->host_arena, s->host_bytes, hipHostMallocCoherent);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->work, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->kernel_done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -291,7 +289,6 @@ xrt_status xrt_server_destroy(xrt_server *s)
         std::lock_guard<std::mutex> g(s->mu);
         __atomic_store_n(&s->ctrl->stop, 1u, __ATOMIC_RELEASE);
         if (s->launched) e = hipEventSynchronize(s->kernel_done);
-        if (e == hipSuccess) e = hipStreamSynchronize(s->copy);
     }
     free_server(s);
     if (e != hipSuccess) return hip_fail(e, "xrt_server_destroy");
