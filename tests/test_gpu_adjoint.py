@@ -180,3 +180,22 @@ def test_autograd_chain_to_physical_parameters():
     say("autograd", auto)
     say("fd      ", fd)
     assert np.all(np.abs(auto - fd) <= 1e-5 * np.abs(fd) + 1e-6 * np.max(np.abs(fd)))
+
+
+def test_rois_split_sums():
+    """Three 24 x 24 regions of the refinement workload (60 000 terms per
+    pixel, 12 tiles in all, so each sum is cut into 58 parts): parity with the
+    oracle, and the same bits as three one-region calls (which split into 58
+    parts too)."""
+    shot, origins = synth.roi_shot()
+    origins = (origins[:3] + 4).astype(np.int32)
+    size = (24, 24)
+    fh = xrt.Fhkl.from_shot(shot)
+    img = xrt.simulate_rois(shot, fh, origins, size, precision="fp64")
+    ref = o.simulate(shot, roi_pixels(origins, size)).reshape(3, 24, 24)
+    r = compare(img.cpu().numpy(), ref)
+    say("rois split fp64", r)
+    assert r["zeros_ok"] and r["max_rel"] <= 1e-12
+    for k, (f0, s0) in enumerate(origins):
+        one = xrt.simulate(shot, fh, precision="fp64", roi=(int(f0), int(f0) + 24, int(s0), int(s0) + 24))
+        assert torch.equal(one, img[k])
