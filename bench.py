@@ -285,6 +285,16 @@ def main():
                         "max_rel_err": emax, "rms_rel_err": erms, "err_sample": "256 seeded pixels"}
         log(f"mixed: {1e3 * wall32 / args.steps:.1f} ms/step, {v32:.1f} Gterm/s, max rel err {emax:.2e}")
 
+    # a small region of the same shot: its sums are split over many
+    # workgroups (a 64 x 64 region is only 16 tiles)
+    small = shot.replace(roi=(1200, 1264, 1250, 1314))
+    res["small_roi"] = {"workload": "64x64 region of the full-size shot (2.46e8 terms, split sums)"}
+    for prec in ("fp64", "mixed"):
+        _, wall_s, ev_s = time_form(small, fh, prec, max(args.steps, 5), 1)
+        ms_s = sum(ev_s) / len(ev_s)
+        res["small_roi"][prec] = {"ms": ms_s, "Gterm_s": small.n_terms / ms_s / 1e6}
+        log(f"small ROI {prec}: {ms_s:.2f} ms, {small.n_terms / ms_s / 1e6:.0f} Gterm/s")
+
     if not args.no_adjoint:
         res["adjoint"] = adjoint_bench(args.steps)
 
