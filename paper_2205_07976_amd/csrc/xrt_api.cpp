@@ -571,6 +571,7 @@ xrt_status served_descriptor(const xrt_detector *det, const xrt_beam *beam, cons
     d->p.out_f64 = out_dtype == XRT_F64;
     d->roi_f0 = det->roi_f0;
     d->roi_s0 = det->roi_s0;
+    d->clamp = pl.clamp ? 1 : 0;
     tables.assign(pl.host.begin(), pl.host.begin() + (ptrdiff_t)pl.o_orig);
     return XRT_OK;
 }

@@ -98,6 +98,8 @@ struct ShotDesc {
     uint64_t partial_off;   // byte offset of the partial sums in the device arena
     uint64_t partial_bytes; // (split > 1 only)
     int32_t roi_f0, roi_s0;
+    int32_t clamp;          // 0: every rint(h) of the shot is proven inside the padded table
+    int32_t pad2;
 };
 
 struct ServeChunk {         // written by the host before the tail publishes it

@@ -416,10 +416,11 @@ hipError_t launch_spots(const Params &p, int precision, bool clamp, hipStream_t 
 // counter, only below the published tail), stage the chunk's shot descriptor
 // and tables in LDS (kept there while the next chunk belongs to the same shot),
 // run the same per-pixel sum as the standalone kernel and set the chunk's done
-// flag.  Served shots always take the clamped table index: it gives the same
-// bits as the clamp-free one whenever the latter is valid, and one variant
-// keeps the kernel within 168 VGPRs (3 waves per SIMD) with the next matrix's
-// LDS reads in flight during each term.  The kernel leaves
+// flag.  Like the standalone kernel, a shot whose every rint(h) the host has
+// proven inside the padded table takes the clamp-free table index (both give
+// the same bits where the clamp-free one is valid); the kernel keeps within 168
+// VGPRs (3 waves per SIMD) with the next matrix's LDS reads in flight during
+// each term.  The kernel leaves
 // only when the whole device is idle: no workgroup holds a chunk, nothing
 // published is unclaimed and no chunk finished for idle_ticks; the first
 // workgroup to see that raises the exit flag and all workgroups leave together
@@ -594,6 +595,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
         }
         const Params p = uniform_params(sd.p);
         const int roi_f0 = uni(sd.roi_f0), roi_s0 = uni(sd.roi_s0);
+        const int clamp = uni(sd.clamp);
         const int n_units = min(max(s_ntiles, 0), SERVE_MAX_CHUNK);
         const int split = p.split;
         const int n_outer = p.O * p.O * p.T * p.n_src;
@@ -616,8 +618,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
             if (s_kind == CHUNK_COMPUTE) {
                 const int i_f = roi_f0 + (lf < p.roi_nf ? lf : p.roi_nf - 1);
                 const int i_s = roi_s0 + (ls < p.roi_ns ? ls : p.roi_ns - 1);
-                sum = pixel_sum<PREC, SHAPE, true, true>(p, tab, smats, ssrc, i_f, i_s, part_begin(k, split, n_outer),
-                                                         part_begin(k + 1, split, n_outer));
+                const int q0 = part_begin(k, split, n_outer), q1 = part_begin(k + 1, split, n_outer);
+                sum = clamp ? pixel_sum<PREC, SHAPE, true, true>(p, tab, smats, ssrc, i_f, i_s, q0, q1)
+                            : pixel_sum<PREC, SHAPE, false, true>(p, tab, smats, ssrc, i_f, i_s, q0, q1);
                 if (split > 1) {
                     if (parts_ok) *reinterpret_cast<double *>(a.arena + pq + 8 * (uint64_t)k * BLOCK) = sum;
                     continue;

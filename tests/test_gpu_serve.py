@@ -220,3 +220,41 @@ def test_served_split_shots(precision):
         r = compare(ref[0], o.simulate(shots[0]))
         say("split shot vs oracle", r)
         assert r["zeros_ok"] and r["max_rel"] <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_served_clamped_shots(precision):
+    """A small structure-factor table ([-20, 20]^3, F_default 3) under the
+    full-size detector: regions near the detector edge reach |h| ~ 60, so those
+    shots take the clamped table index (and the default value), the central
+    ones the clamp-free index; each image equals the standalone call's bit for
+    bit, in one mix."""
+    tiny = synth.tiny_shot()
+    base = synth.full_shot()
+    rng = np.random.default_rng(31)
+    shots = []
+    for k in range(6):
+        s = synth.served_shot(rng, tiny.F, tiny.hkl_min).replace(F_default=3.0)
+        n_src, n_mos = int(rng.integers(2, 9)), int(rng.integers(2, 9))
+        w = 48
+        f0 = [0, 2463 - w, 1200, 0, 2463 - w, 1230][k]
+        s0 = [0, 2527 - w, 1250, 2527 - w, 0, 1240][k]
+        s = s.replace(roi=(f0, f0 + w, s0, s0 + w), src_dir=s.src_dir[:n_src].copy(),
+                      src_lambda=s.src_lambda[:n_src].copy(),
+                      src_weight=s.src_weight[:n_src] / s.src_weight[:n_src].sum(), umats=s.umats[:n_mos].copy())
+        assert s.n_fast == base.n_fast and s.n_slow == base.n_slow
+        shots.append(s)
+    fh = xrt.Fhkl.from_shot(shots[0])
+    ref = [xrt.simulate(s, fh, precision=precision).cpu().numpy() for s in shots]
+    srv = xrt.Server(fh, hbm_budget=64 << 20, precision=precision)
+    tickets = [srv.submit(s) for s in shots]
+    drain(srv, tickets)
+    for i, t in enumerate(tickets):
+        assert np.array_equal(srv.image(t).cpu().numpy(), ref[i]), f"shot {i} differs"
+        srv.release(t)
+    srv.close()
+    # the edge regions do reach outside the table: their default-valued terms
+    # make them differ from a run with F_default = 0
+    fh0 = xrt.Fhkl.from_shot(shots[0].replace(F_default=0.0))
+    edge0 = xrt.simulate(shots[0], fh0, precision=precision).cpu().numpy()
+    assert not np.array_equal(edge0, ref[0])
