@@ -11,13 +11,17 @@
 //    wave touches a handful of table lines;
 //  * workgroup ids are remapped so that each of the 8 XCDs (dispatched
 //    round-robin) gets one contiguous band of tiles and keeps the part of the
-//    F^2 table its band needs in its own L2;
+//    F^2 table its band needs in its own L2 (a small effect: the vector L1
+//    already serves nearly every gather);
 //  * the per-shot tables (cell matrices, sources) are indexed by loop
-//    counters that are the same for the whole wave, so they are read with
-//    scalar loads into SGPRs;
+//    counters that are the same for the whole wave, so the standalone kernel
+//    reads them with scalar loads into SGPRs (the persistent served kernel
+//    stages them in LDS);
 //  * loop order: sub-pixel and layer (geometry in binary64), source (S, P),
 //    then the inner loop over spindle steps and mosaic domains, which is the
-//    hot loop; the per-pixel result is stored once, coalesced per row.
+//    hot loop; the per-pixel result is stored once, coalesced per row;
+//  * small regions split each pixel's outer iterations into parts summed by
+//    different workgroups and added in part order afterwards.
 //
 // The file is compiled with -ffp-contract=off: S and h follow a fixed
 // operation sequence (below), and every fused multiply-add is explicit.
