@@ -302,6 +302,12 @@ xrt_status xrt_server_image(xrt_server *srv, uint64_t ticket, const void **dev_i
 /* Free a finished shot's memory and slot.  EBUSY if not done. */
 xrt_status xrt_server_release(xrt_server *srv, uint64_t ticket);
 
+/* Withdraw a shot that is still queued (not yet admitted): the ticket is
+ * forgotten and the shots behind it move up.  EBUSY once the shot has been
+ * admitted (its work may be on the device: wait for it and release it);
+ * EINVAL for an unknown ticket. */
+xrt_status xrt_server_cancel(xrt_server *srv, uint64_t ticket);
+
 /* Diagnostics: the kernels' sin(pi x) for |x| <= 1/2 (the reduced arguments f
  * and g of the lattice factor, section II's crystal-size transform), exactly
  * as the binary64 kernel (dev_s64) and the mixed kernel (dev_s32, from

@@ -217,6 +217,17 @@ class Scheduler {
         inflight_.resize(k);
     }
 
+    // Withdraw a shot that is still queued (it holds no space and no chunk
+    // of it exists).  Returns false if the shot is unknown or was admitted.
+    bool cancel(uint64_t ticket)
+    {
+        auto it = work_.find(ticket);
+        if (it == work_.end() || it->second.state != QUEUED) return false;
+        queue_.erase(std::find(queue_.begin(), queue_.end(), ticket));
+        work_.erase(it);
+        return true;
+    }
+
     // Forget a finished shot and free its space.  Returns false if the shot
     // is unknown or not done.
     bool release(uint64_t ticket)

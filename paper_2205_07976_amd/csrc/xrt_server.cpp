@@ -387,6 +387,19 @@ xrt_status xrt_server_image(xrt_server *s, uint64_t ticket, const void **dev_ima
     return XRT_OK;
 }
 
+xrt_status xrt_server_cancel(xrt_server *s, uint64_t ticket)
+{
+    if (!s) return fail(XRT_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> g(s->mu);
+    const xrt::sched::Work *w = s->sched->find(ticket);
+    if (!w) return fail(XRT_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    if (w->state != xrt::sched::QUEUED)
+        return fail(XRT_EBUSY, "shot %llu is already admitted", (unsigned long long)ticket);
+    s->sched->cancel(ticket);
+    s->shots.erase(ticket);
+    return XRT_OK;
+}
+
 xrt_status xrt_server_release(xrt_server *s, uint64_t ticket)
 {
     if (!s) return fail(XRT_EINVAL, "server is NULL");

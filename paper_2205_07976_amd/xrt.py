@@ -96,7 +96,7 @@ _lib = None
 SYMBOLS = ("xrt_version", "xrt_last_error", "xrt_fhkl_create", "xrt_fhkl_destroy",
            "xrt_simulate", "xrt_simulate_rois", "xrt_backward_rois", "xrt_server_create",
            "xrt_server_destroy", "xrt_server_submit", "xrt_server_progress", "xrt_server_info",
-           "xrt_server_image", "xrt_server_release", "xrt_cell_mats", "xrt_trace_terms", "xrt_sinpi", "xrt_exp")
+           "xrt_server_image", "xrt_server_release", "xrt_server_cancel", "xrt_cell_mats", "xrt_trace_terms", "xrt_sinpi", "xrt_exp")
 XRT_SHOT_QUEUED, XRT_SHOT_RUNNING, XRT_SHOT_DONE = 0, 1, 2
 
 
@@ -128,6 +128,7 @@ def load():
     lib.xrt_server_info.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(ShotInfo)]
     lib.xrt_server_image.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_void_p)]
     lib.xrt_server_release.argtypes = [C.c_void_p, C.c_uint64]
+    lib.xrt_server_cancel.argtypes = [C.c_void_p, C.c_uint64]
     lib.xrt_cell_mats.argtypes = [C.POINTER(Crystal), C.c_void_p]
     lib.xrt_trace_terms.argtypes = [C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal), C.c_int64,
                                     C.c_void_p, C.c_void_p, C.c_void_p]
@@ -391,6 +392,10 @@ class Server:
 
     def release(self, ticket):
         _check(load().xrt_server_release(self._h, int(ticket)))
+
+    def cancel(self, ticket):
+        """Withdraw a shot that is still queued; XrtError (EBUSY) once admitted."""
+        _check(load().xrt_server_cancel(self._h, int(ticket)))
 
     def close(self):
         if self._h is not None and self._h.value:

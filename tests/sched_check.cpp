@@ -252,6 +252,33 @@ static void check_fair_share()
     CHECK(n2 * 10 >= n3 * 8 && n3 * 10 >= n2 * 8);  // equal-cost chunks: equal counts, within 20 %
 }
 
+static void check_cancel()
+{
+    printf("cancel: queued shots only; the ones behind move up; space untouched\n");
+    Scheduler s(1000, 1 << 20, 8, 4, 1 << 16);
+    Device d(s);
+    s.submit(shot(1, 600, 4, 1000));
+    s.submit(shot(2, 600, 4, 1000));
+    s.submit(shot(3, 300, 4, 1000));
+    s.admit([](Work &) { return 0; });
+    CHECK(s.find(1)->state == RUNNING && s.find(2)->state == QUEUED);
+    CHECK(!s.cancel(1));                    // admitted: not cancellable
+    CHECK(!s.cancel(99));                   // unknown
+    CHECK(s.cancel(2));                     // queued head behind the running shot
+    CHECK(s.find(2) == nullptr);
+    s.admit([](Work &) { return 0; });
+    CHECK(s.find(3)->state == RUNNING);     // moved up and fits beside shot 1
+    for (int i = 0; i < 1000 && (s.find(1)->state != DONE || s.find(3)->state != DONE); ++i) {
+        d.publish();
+        d.run(10, true);
+        d.collect();
+    }
+    for (const Chunk &c : d.log) CHECK(c.ticket != 2);
+    CHECK(s.release(1) && s.release(3));
+    CHECK(s.dev_arena().free_blocks().size() == 1 && s.dev_arena().free_blocks().begin()->second == 1000);
+    CHECK(s.host_arena().free_blocks().begin()->second == (1u << 20));
+}
+
 static void check_ring_sequence()
 {
     printf("ring: sequence numbers increase by one across many wraps\n");
@@ -277,6 +304,7 @@ int main()
     check_fifo_admission();
     check_units_and_depth();
     check_fair_share();
+    check_cancel();
     check_ring_sequence();
     printf("all scheduler checks passed\n");
     return 0;

@@ -160,3 +160,11 @@ def test_header_is_plain_c(tmp_path):
     src.write_text('#include "include/xrt.h"\nint main(void) { xrt_detector d; (void)d; return XRT_OK; }\n')
     subprocess.run([cc, "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror", "-I", root, "-c", str(src),
                     "-o", str(tmp_path / "use.o")], check=True)
+
+
+def test_server_calls_reject_null():
+    lib = xrt.load()
+    assert lib.xrt_server_cancel(None, 1) == xrt.XRT_EINVAL
+    assert lib.xrt_server_release(None, 1) == xrt.XRT_EINVAL
+    assert lib.xrt_server_progress(None, None) == xrt.XRT_EINVAL
+    assert lib.xrt_server_destroy(None) == xrt.XRT_OK

@@ -258,3 +258,37 @@ def test_served_clamped_shots(precision):
     fh0 = xrt.Fhkl.from_shot(shots[0].replace(F_default=0.0))
     edge0 = xrt.simulate(shots[0], fh0, precision=precision).cpu().numpy()
     assert not np.array_equal(edge0, ref[0])
+
+
+def test_cancel_queued_shots():
+    """With room for one shot at a time, the queued shots behind the first can
+    be withdrawn; an admitted one cannot; the rest still equal their
+    standalone images."""
+    base, shots = small_served_shots(5, seed=41, max_side=64)
+    shots = [s.replace(roi=(100 + 9 * i, 100 + 9 * i + 400, 300, 300 + 400)) for i, s in enumerate(shots)]
+    fh = xrt.Fhkl.from_shot(base)
+    srv = xrt.Server(fh, hbm_budget=1 << 20, max_resident=1, precision="mixed")  # one 400 x 400 image fits
+    tickets = [srv.submit(s) for s in shots]
+    srv.progress()
+    assert srv.info(tickets[0]).state == xrt.XRT_SHOT_RUNNING
+    with pytest.raises(xrt.XrtError) as e:
+        srv.cancel(tickets[0])
+    assert e.value.code == xrt.XRT_EBUSY
+    srv.cancel(tickets[1])
+    srv.cancel(tickets[3])
+    with pytest.raises(xrt.XrtError):
+        srv.info(tickets[1])
+    keep = [0, 2, 4]
+    t0 = time.time()
+    pending = [tickets[i] for i in keep]
+    while pending:
+        srv.progress()
+        for t in list(pending):
+            if srv.info(t).state == xrt.XRT_SHOT_DONE:
+                i = tickets.index(t)
+                assert np.array_equal(srv.image(t).cpu().numpy(),
+                                      xrt.simulate(shots[i], fh, precision="mixed").cpu().numpy())
+                srv.release(t)
+                pending.remove(t)
+        assert time.time() - t0 < 60
+    srv.close()
