@@ -523,6 +523,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     // idle workgroups stay off the memory paths the busy ones use
     const int max_backoff = blockIdx.x < 8 ? 16 : 256;
     int backoff = 1;
+    // the idle time counts from the launch (the host zeroes last_done)
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_max(a.last_done, (unsigned long long)__builtin_amdgcn_s_memrealtime(), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
         if (threadIdx.x == 0) {
             long long c = -2;
