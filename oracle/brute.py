@@ -11,6 +11,10 @@ differs from the C oracle on purpose wherever a choice exists:
 * the cell matrices built as full matrix products umat * R_phi * U;
 * the loops nested in another order (domain, source, then sample point).
 
+The background of an amorphous scatterer is restated the same way
+(``background``): stol from the scattering angle instead of |S|/2, the curve
+by bisection instead of a scan.
+
 Pure-Python loops: only for a handful of pixels.
 """
 from __future__ import annotations
@@ -129,6 +133,69 @@ def simulate(shot, pixels):
             norm = (R_E ** 2 * mp.mpf(float(shot.fluence)) * mp.mpf(float(shot.scale))
                     / (O * O * shot.n_phi * shot.n_mos))
             res.append(norm * total)
+        return res
+
+
+def _bg_curve(stol, F, x):
+    """Piecewise-linear interpolation by bisection over the knots (the C oracle
+    scans them), constant beyond the ends."""
+    import bisect
+    xs = [mp.mpf(float(v)) for v in stol]
+    if x <= xs[0]:
+        return mp.mpf(float(F[0]))
+    if x >= xs[-1]:
+        return mp.mpf(float(F[-1]))
+    k = bisect.bisect_right(xs, x) - 1
+    a, b = mp.mpf(float(F[k])), mp.mpf(float(F[k + 1]))
+    return (a * (xs[k + 1] - x) + b * (x - xs[k])) / (xs[k + 1] - xs[k])
+
+
+def background(shot, bg, pixels):
+    """Background of an amorphous scatterer (mpf) at the given pixels, from
+    angles: stol = sin(theta)/lambda with 2 theta = acos(d . inc), and the
+    polarization from explicit 2 theta and psi; loops source-outermost."""
+    with mp.workdps(DPS):
+        O = shot.oversample
+        fdet, sdet, odet = _vec(shot.fdet), _vec(shot.sdet), _vec(shot.odet)
+        p = mp.mpf(float(shot.pixel))
+        D = mp.mpf(float(shot.distance))
+        dt = mp.mpf(float(shot.layer_dt))
+        mu = mp.mpf(float(shot.atten_len))
+        K = mp.mpf(float(shot.kahn))
+        e = _vec(shot.evec)
+        res = []
+        for (i_f, i_s) in pixels:
+            total = mp.mpf(0)
+            for j in range(shot.n_src):
+                inc = _vec(shot.src_dir[j])
+                lam = mp.mpf(float(shot.src_lambda[j]))
+                w = mp.mpf(float(shot.src_weight[j]))
+                ep = e - _dot(e, inc) * inc
+                ep = ep / mp.sqrt(_dot(ep, ep))
+                b = _cross(inc, ep)
+                for t in range(shot.n_layers):
+                    for u in range(O):
+                        for v in range(O):
+                            Fp = (int(i_f) + (v + mp.mpf(1) / 2) / O) * p - mp.mpf(float(shot.beam_f))
+                            Sp = (int(i_s) + (u + mp.mpf(1) / 2) / O) * p - mp.mpf(float(shot.beam_s))
+                            r = Fp * fdet + Sp * sdet + (D + t * dt) * odet
+                            R = mp.sqrt(_dot(r, r))
+                            d = r / R
+                            cosrho = _dot(d, odet)
+                            dom = p * p * cosrho / (R * R)
+                            if dt == 0:
+                                cap = mp.mpf(1)
+                            else:
+                                cap = (mp.exp(-t * dt / (mu * cosrho))
+                                       - mp.exp(-(t + 1) * dt / (mu * cosrho)))
+                            two_theta = mp.acos(_dot(d, inc))
+                            psi = mp.atan2(_dot(d, b), _dot(d, ep))
+                            P = (1 + mp.cos(two_theta) ** 2
+                                 - K * mp.cos(2 * psi) * mp.sin(two_theta) ** 2) / 2
+                            Fb = _bg_curve(bg.stol, bg.F, mp.sin(two_theta / 2) / lam)
+                            total += w * P * dom * cap * Fb * Fb
+            res.append(R_E ** 2 * mp.mpf(float(shot.fluence)) * mp.mpf(float(bg.molecules))
+                       / (O * O) * total)
         return res
 
 

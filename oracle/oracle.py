@@ -55,6 +55,10 @@ class _Shot(C.Structure):
     ]
 
 
+class _Bg(C.Structure):
+    _fields_ = [("n_knots", C.c_int32), ("stol", _pd), ("F", _pd), ("molecules", C.c_double)]
+
+
 _lib = None
 
 
@@ -75,6 +79,10 @@ def _load():
         lib.xro_capture.restype = C.c_double
         lib.xro_gradient.argtypes = [C.POINTER(_Shot), C.c_int64, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_int]
+        lib.xro_bg_curve.argtypes = [C.POINTER(_Bg), C.c_double]
+        lib.xro_bg_curve.restype = C.c_double
+        lib.xro_background.argtypes = [C.POINTER(_Shot), C.POINTER(_Bg), C.c_int64, C.c_void_p,
+                                       C.c_void_p, C.c_int]
         _lib = lib
     return _lib
 
@@ -178,3 +186,35 @@ def gradient(shot, pixels, dLdI, nthreads: int = 0) -> np.ndarray:
                         out.ctypes.data, int(nthreads)):
         raise MemoryError("oracle: allocation failed")
     return out
+
+
+class _PackedBg:
+    def __init__(self, bg):
+        self.keep = [_arr(bg.stol), _arr(bg.F)]
+        b = _Bg()
+        b.n_knots = len(self.keep[0])
+        b.stol = self.keep[0].ctypes.data_as(_pd)
+        b.F = self.keep[1].ctypes.data_as(_pd)
+        b.molecules = float(bg.molecules)
+        self.s = b
+
+
+def bg_curve(bg, x) -> np.ndarray:
+    """The scattering curve of a ``synth.Background`` at each stol of x."""
+    lib = _load()
+    pb = _PackedBg(bg)
+    return np.array([lib.xro_bg_curve(C.byref(pb.s), float(v)) for v in np.ravel(x)])
+
+
+def background(shot, bg, pixels=None, nthreads: int = 0) -> np.ndarray:
+    """FP64 background of an amorphous scatterer (``synth.Background``) over
+    the shot's detector and beam; ``pixels`` as for ``simulate``."""
+    lib = _load()
+    pk = _Packed(shot)
+    pb = _PackedBg(bg)
+    full = pixels is None
+    pix = _arr(shot.pixel_list() if full else pixels, np.int32)
+    out = np.empty(len(pix), np.float64)
+    lib.xro_background(C.byref(pk.s), C.byref(pb.s), len(pix), pix.ctypes.data, out.ctypes.data,
+                       int(nthreads))
+    return out.reshape(shot.roi_shape) if full else out

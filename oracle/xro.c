@@ -24,7 +24,8 @@
  * P_j the Kahn polarization factor, dOmega the solid angle of the sample point
  * and capture the Beer-Lambert fraction absorbed in the sensor layer.
  *
- * Every sum is Neumaier-compensated (Neumaier 1974).
+ * Every sum is Neumaier-compensated (Neumaier 1974).  The background of an
+ * amorphous scatterer (air, water) is at the end of the file.
  *
  * Evaluation contract.  A lattice factor near a zero of sin(pi N f) is
  * ill-conditioned in h, so S and h are computed with one fixed operation
@@ -386,5 +387,64 @@ int xro_gradient(const xro_shot *s, int64_t n, const int32_t *pix, const double 
         grad13[i] = ksum_get(&k);
     }
     free(mats); free(qmats); free(part);
+    return 0;
+}
+
+/* ---- background of an amorphous scatterer --------------------------------
+ * Section III lists, beside the spots kernel, a kernel that adds the
+ * background scattered by the air and the water around the crystal; the
+ * paper gives no formula for it.  An amorphous scatterer has no lattice: the
+ * molecules scatter independently, and what one molecule scatters depends on
+ * the scattering angle only, through sin(theta)/lambda = |S|/2, by its
+ * scattering curve F_bg.  With the sample points, S, P, dOmega and capture of
+ * the spots sum:
+ *
+ *   I_bg(pixel) = r_e^2 * fluence * molecules / O^2
+ *               * sum_{sub-pixel, layer}  dOmega * capture
+ *                 * sum_{source j}  w_j * P_j * F_bg(|S_j| / 2)^2
+ *
+ * No spindle or mosaic average: the scatterer has no orientation. */
+double xro_bg_curve(const xro_bg *bg, double x)
+{
+    const int n = bg->n_knots;
+    const double *s = bg->stol, *F = bg->F;
+    if (x <= s[0]) return F[0];
+    if (x >= s[n - 1]) return F[n - 1];
+    int k = 0;
+    while (s[k + 1] <= x) ++k; /* s[k] <= x < s[k+1] */
+    double t = (x - s[k]) / (s[k + 1] - s[k]);
+    return F[k] + t * (F[k + 1] - F[k]);
+}
+
+static double bg_pixel(const xro_shot *s, const xro_bg *bg, int i_f, int i_s)
+{
+    const int O = s->oversample;
+    ksum acc = {0.0, 0.0};
+    for (int u = 0; u < O; ++u)
+        for (int v = 0; v < O; ++v)
+            for (int t = 0; t < s->n_layers; ++t) {
+                sample_pt sp;
+                sample_point(s, i_f, i_s, u, v, t, &sp);
+                for (int j = 0; j < s->n_src; ++j) {
+                    double S[3];
+                    scatter_vec(s, &sp, j, S);
+                    double F = xro_bg_curve(bg, 0.5 * sqrt(dot3(S, S)));
+                    double P = xro_polarization(sp.d, s->src_dir + 3 * (size_t)j, s->evec, s->kahn);
+                    ksum_add(&acc, s->src_weight[j] * P * sp.domega * sp.capture * F * F);
+                }
+            }
+    double Od = (double)O;
+    return XRO_RE * XRO_RE * s->fluence * bg->molecules / (Od * Od) * ksum_get(&acc);
+}
+
+int xro_background(const xro_shot *s, const xro_bg *bg, int64_t n, const int32_t *pix,
+                   double *out, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+    for (int64_t p = 0; p < n; ++p)
+        out[p] = bg_pixel(s, bg, pix[2 * p], pix[2 * p + 1]);
     return 0;
 }

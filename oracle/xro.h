@@ -78,6 +78,25 @@ double xro_capture(int32_t t, double dt, double mu, double cosrho);
 int xro_gradient(const xro_shot *s, int64_t n, const int32_t *pix,
                  const double *dLdI, double *grad13, int nthreads);
 
+/* An amorphous scatterer around the crystal (air, water): a scattering curve
+ * F_bg(stol) given by n_knots (stol_k, F_k) pairs, stol = sin(theta)/lambda
+ * strictly increasing, and the number of molecules in the beam. */
+typedef struct xro_bg {
+    int32_t n_knots;
+    const double *stol;
+    const double *F;
+    double molecules;
+} xro_bg;
+
+/* F_bg at one stol: the piecewise-linear interpolant of the knots, constant
+ * beyond the first and the last knot. */
+double xro_bg_curve(const xro_bg *bg, double stol);
+
+/* Background of n pixels given as (i_fast, i_slow) pairs; the crystal fields
+ * of the shot are not used. */
+int xro_background(const xro_shot *s, const xro_bg *bg, int64_t n, const int32_t *pix,
+                   double *out, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -374,3 +374,54 @@ def roi_shot(seed: int = 5, n_roi: int = 512, size: int = 32, lam0: float = 1.30
     if len(chosen) < n_roi:
         raise ValueError(f"only {len(chosen)} non-overlapping spots found")
     return shot, np.array(chosen, dtype=np.int32)
+
+
+# ---------------------------------------------------------------------------
+# background scatterers
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Background:
+    """An amorphous scatterer around the crystal (air, water): a scattering
+    curve given as knots (stol_k, F_k), stol = sin(theta)/lambda in 1/angstrom
+    strictly increasing, F per molecule; and the number of molecules in the
+    beam."""
+    stol: np.ndarray
+    F: np.ndarray
+    molecules: float
+
+    @property
+    def n_knots(self) -> int:
+        return int(len(self.stol))
+
+
+def _knots(rng: np.random.Generator, n: int, top: float, power: float) -> np.ndarray:
+    """n increasing knots on [0, top], denser at small stol (exponent power),
+    each interior knot moved by up to a fifth of its gap (seeded)."""
+    x = top * (np.arange(n) / (n - 1)) ** power
+    gap = np.diff(x)
+    x[1:-1] += rng.uniform(-0.2, 0.2, n - 2) * np.minimum(gap[:-1], gap[1:])
+    return x
+
+
+def water_background(seed: int = 7, n_knots: int = 48, molecules: float = 1.0e11) -> Background:
+    """A liquid-water-like curve: a ring near stol = 0.16 / A (the 3.1 A
+    oxygen-oxygen distance) on a slowly decaying base, knots on [0, 1.2] / A
+    with a 2 % seeded jitter of the values.  A synthetic stand-in: the paper
+    gives no background curve."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = _knots(rng, n_knots, 1.2, 1.5)
+    F = (1.0 + 1.6 * np.exp(-(((s - 0.16) / 0.06) ** 2)) + 1.2 * np.exp(-((s / 0.6) ** 2)))
+    F *= 1.0 + 0.02 * rng.uniform(-1.0, 1.0, n_knots)
+    return Background(stol=s, F=F, molecules=molecules)
+
+
+def air_background(seed: int = 8, n_knots: int = 24, molecules: float = 4.0e10) -> Background:
+    """A gas-like curve: forward scattering of a 14-electron molecule falling
+    off monotonically, knots on [0, 1.0] / A.  Synthetic, like
+    water_background."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = _knots(rng, n_knots, 1.0, 1.3)
+    F = 14.0 * np.exp(-((s / 0.35) ** 2)) + 0.5
+    F *= 1.0 + 0.01 * rng.uniform(-1.0, 1.0, n_knots)
+    return Background(stol=s, F=F, molecules=molecules)
