@@ -221,6 +221,46 @@ xrt_status xrt_backward_rois(const xrt_detector *det, const xrt_beam *beam,
                              int32_t roi_ns, const void *dev_dLdI,
                              int32_t dLdI_dtype, double *dev_grad13, void *stream);
 
+/* Background of an amorphous scatterer around the crystal (section III's
+ * second kernel, which adds the scattering of the air and the water around
+ * the crystal).  The paper gives no formula; the library computes, for every
+ * pixel of the detector's region of interest,
+ *
+ *   I_bg = r_e^2 * fluence * molecules / O^2
+ *          * sum_{u,v < O} sum_{t < n_layers}  dOmega * capture_t
+ *            * sum_{j < n_src}  w_j * P_j * F_bg(|S_j| / 2)^2
+ *
+ * with the sample points, S, P_j, dOmega and capture_t of xrt_simulate and
+ * F_bg the piecewise-linear interpolant of the curve's knots (constant below
+ * the first and above the last).  |S|/2 = sin(theta)/lambda.  The scatterer
+ * has no orientation: no spindle or mosaic average. */
+typedef struct xrt_background {
+    uint32_t struct_size;
+    int32_t n_knots;               /* knots of the scattering curve, [2, 1024] */
+    const double *stol;            /* host [n_knots] sin(theta)/lambda, 1/angstrom,
+                                      finite, strictly increasing */
+    const double *F;               /* host [n_knots] scattering factor of one
+                                      molecule (finite; every knot and slope
+                                      must also be finite in binary32) */
+    double molecules;              /* scattering molecules in the beam (>= 0) */
+} xrt_background;
+
+/* Background over the detector's region of interest, one kernel on `stream`.
+ *  precision   XRT_FP64: every step in binary64.  XRT_MIXED: sample-point
+ *              geometry and d - dir_j in binary64; |S|/2, the curve, P_j and
+ *              the products in binary32; per-pixel sums compensated (Kahan)
+ *              in binary32.
+ *  dev_image   device pointer, [roi rows][roi cols] of out_dtype.
+ *  accumulate  0: overwrite; 1: add to the image (a background on top of
+ *              xrt_simulate's spots, or several scatterers one after another).
+ * The curve and the sources are copied stream-ordered; host arrays are read
+ * during the call only.
+ * Errors: EINVAL / ERANGE / EVERSION on any malformed field, ENOMEM, EDEVICE. */
+xrt_status xrt_simulate_background(const xrt_detector *det, const xrt_beam *beam,
+                                   const xrt_background *bg, int32_t precision,
+                                   void *dev_image, int32_t out_dtype, int32_t accumulate,
+                                   void *stream);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of independent shots on one device.
  *

@@ -127,6 +127,28 @@ xrt_status check_beam(const xrt_beam *b)
     return XRT_OK;
 }
 
+xrt_status check_background(const xrt_background *g)
+{
+    if (!g) return fail(XRT_EINVAL, "background is NULL");
+    if (g->struct_size != sizeof(xrt_background))
+        return fail(XRT_EVERSION, "xrt_background.struct_size %u, library expects %zu", g->struct_size,
+                    sizeof(xrt_background));
+    if (g->n_knots < 2 || g->n_knots > xrt::BG_MAX_KNOTS)
+        return fail(XRT_ERANGE, "n_knots must be in [2, %d]", xrt::BG_MAX_KNOTS);
+    if (!g->stol || !g->F) return fail(XRT_EINVAL, "curve arrays must not be NULL");
+    if (!is_fin(g->molecules) || g->molecules < 0) return fail(XRT_EINVAL, "molecules must be finite and >= 0");
+    for (int k = 0; k < g->n_knots; ++k) {
+        if (!is_fin(g->stol[k]) || !is_fin(g->F[k])) return fail(XRT_EINVAL, "knot %d is not finite", k);
+        if (k > 0 && !(g->stol[k] > g->stol[k - 1]))
+            return fail(XRT_EINVAL, "knot %d: stol must increase strictly", k);
+        if (k > 0 && !is_fin((float)((g->F[k] - g->F[k - 1]) / (g->stol[k] - g->stol[k - 1]))))
+            return fail(XRT_EINVAL, "knots %d and %d: the slope is not finite in binary32", k - 1, k);
+        if (!is_fin((float)g->stol[k]) || !is_fin((float)g->F[k]))
+            return fail(XRT_ERANGE, "knot %d does not fit binary32", k);
+    }
+    return XRT_OK;
+}
+
 xrt_status check_crystal(const xrt_crystal *x)
 {
     if (!x) return fail(XRT_EINVAL, "crystal is NULL");
@@ -206,8 +228,8 @@ void build_rotations(const xrt_crystal *x, double *out)
     }
 }
 
-// Source rows: direction, wavelength, weight and the polarization basis
-// e_perp = unit(evec - (evec . dir) dir), b = dir x e_perp.
+// Source rows: direction, wavelength, weight, the polarization basis
+// e_perp = unit(evec - (evec . dir) dir), b = dir x e_perp, and 1/(2 lambda).
 void build_sources(const xrt_beam *b, double *out)
 {
     for (int j = 0; j < b->n_src; ++j) {
@@ -217,6 +239,7 @@ void build_sources(const xrt_beam *b, double *out)
         for (int i = 0; i < 3; ++i) row[xrt::SRC_DIR + i] = d[i];
         row[xrt::SRC_LAMBDA] = b->lambda[j];
         row[xrt::SRC_WEIGHT] = b->weight[j];
+        row[xrt::SRC_HIL] = 0.5 / b->lambda[j];
         const double ed = dot3(b->evec, d);
         double e[3];
         for (int i = 0; i < 3; ++i) e[i] = b->evec[i] - ed * d[i];
@@ -231,9 +254,8 @@ void build_sources(const xrt_beam *b, double *out)
     }
 }
 
-// Geometry and lattice fields of the kernel parameters (everything except
-// tables and output).
-void fill_params(const xrt_detector *d, const xrt_beam *b, const xrt_crystal *x, xrt::Params &p)
+// Detector and beam fields of the kernel parameters.
+void fill_geometry(const xrt_detector *d, const xrt_beam *b, xrt::Params &p)
 {
     std::memset(&p, 0, sizeof p);
     p.pixel = d->pixel;
@@ -250,6 +272,14 @@ void fill_params(const xrt_detector *d, const xrt_beam *b, const xrt_crystal *x,
     p.O = d->oversample;
     p.T = d->n_layers;
     p.n_src = b->n_src;
+    p.kahn = b->kahn;
+}
+
+// Geometry and lattice fields of the kernel parameters (everything except
+// tables and output).
+void fill_params(const xrt_detector *d, const xrt_beam *b, const xrt_crystal *x, xrt::Params &p)
+{
+    fill_geometry(d, b, p);
     p.n_rot = x->n_phi * x->n_mos;
     p.shape = x->shape;
     double ln = 0.0;
@@ -261,7 +291,6 @@ void fill_params(const xrt_detector *d, const xrt_beam *b, const xrt_crystal *x,
         ln += 2.0 * std::log(x->N[i]);
     }
     p.ln_n2 = ln;
-    p.kahn = b->kahn;
     const double O = (double)d->oversample;
     p.norm = R_E * R_E * b->fluence * x->scale / (O * O * (double)x->n_phi * (double)x->n_mos);
 }
@@ -664,6 +693,74 @@ xrt_status xrt_backward_rois(const xrt_detector *det, const xrt_beam *beam, cons
     if (e != hipSuccess) return hip_fail(e, "xrt_backward_rois");
     if (e2 != hipSuccess) return hip_fail(e2, "xrt_backward_rois");
     if (e3 != hipSuccess) return hip_fail(e3, "xrt_backward_rois");
+    return XRT_OK;
+}
+
+xrt_status xrt_simulate_background(const xrt_detector *det, const xrt_beam *beam, const xrt_background *bg,
+                                   int32_t precision, void *dev_image, int32_t out_dtype, int32_t accumulate,
+                                   void *stream)
+{
+    xrt_status st;
+    if ((st = check_call(precision, out_dtype, dev_image, "dev_image"))) return st;
+    if (accumulate != 0 && accumulate != 1) return fail(XRT_EINVAL, "accumulate must be 0 or 1");
+    if ((st = check_detector(det)) || (st = check_beam(beam)) || (st = check_background(bg))) return st;
+    if ((st = check_roi(det, det->roi_f0, det->roi_f1, det->roi_s0, det->roi_s1, 0))) return st;
+    const int32_t nf = det->roi_f1 - det->roi_f0, ns = det->roi_s1 - det->roi_s0;
+    const int n = bg->n_knots, n_src = beam->n_src;
+
+    // one upload: [sources | origin | knots | sources (binary32) | knots (binary32)]
+    const size_t o_orig = xrt::SRC_STRIDE * (size_t)n_src, o_k64 = o_orig + 1, o_s32 = o_k64 + 3 * (size_t)n;
+    const size_t o_k32 = o_s32 + (xrt::SRC_STRIDE * (size_t)n_src + 1) / 2;
+    std::vector<double> host(o_k32 + (3 * (size_t)n + 1) / 2, 0.0);
+    build_sources(beam, host.data());
+    const int32_t origin[2] = {det->roi_f0, det->roi_s0};
+    std::memcpy(host.data() + o_orig, origin, sizeof origin);
+    double *k64 = host.data() + o_k64;
+    float *s32 = reinterpret_cast<float *>(host.data() + o_s32);
+    float *k32 = reinterpret_cast<float *>(host.data() + o_k32);
+    for (int k = 0; k < n; ++k) {
+        k64[3 * k] = bg->stol[k];
+        k64[3 * k + 1] = bg->F[k];
+        k64[3 * k + 2] = k + 1 < n ? (bg->F[k + 1] - bg->F[k]) / (bg->stol[k + 1] - bg->stol[k]) : 0.0;
+        for (int c = 0; c < 3; ++c) k32[3 * k + c] = (float)k64[3 * k + c];
+    }
+    for (size_t i = 0; i < xrt::SRC_STRIDE * (size_t)n_src; ++i) s32[i] = (float)host[i];
+
+    xrt::BgParams b;
+    std::memset(&b, 0, sizeof b);
+    xrt::Params &p = b.p;
+    fill_geometry(det, beam, p);
+    p.roi_nf = nf;
+    p.roi_ns = ns;
+    p.tiles_f = (nf + 15) / 16;
+    p.tiles_per_roi = p.tiles_f * ((ns + 15) / 16);
+    p.n_roi = 1;
+    p.n_tiles = p.tiles_per_roi;
+    p.split = 1;
+    const double O = (double)det->oversample;
+    p.norm = R_E * R_E * beam->fluence * bg->molecules / (O * O);
+    p.image = dev_image;
+    p.out_f64 = out_dtype == XRT_F64;
+    p.accumulate = accumulate;
+    b.n_knots = n;
+    b.n_pad = 1;
+    while (b.n_pad < n) b.n_pad *= 2;
+
+    hipStream_t s = (hipStream_t)stream;
+    double *tables = nullptr;
+    HIP_TRY(hipMallocAsync((void **)&tables, sizeof(double) * host.size(), s), "hipMallocAsync");
+    hipError_t e = hipMemcpyAsync(tables, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        p.src = tables;
+        p.origins = reinterpret_cast<const int32_t *>(tables + o_orig);
+        b.knots64 = tables + o_k64;
+        b.src32 = reinterpret_cast<const float *>(tables + o_s32);
+        b.knots32 = reinterpret_cast<const float *>(tables + o_k32);
+        e = xrt::launch_background(b, precision, s);
+    }
+    hipError_t e2 = hipFreeAsync(tables, s);
+    if (e != hipSuccess) return hip_fail(e, "xrt_simulate_background");
+    if (e2 != hipSuccess) return hip_fail(e2, "xrt_simulate_background");
     return XRT_OK;
 }
 

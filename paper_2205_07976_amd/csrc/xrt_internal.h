@@ -9,11 +9,12 @@
 
 namespace xrt {
 
-// Per-source table row: propagation direction, wavelength, weight, and the
+// Per-source table row: propagation direction, wavelength, weight, the
 // polarization basis (e_perp, dir x e_perp) in which the azimuth psi is
-// measured.  Padded to 12 doubles (96 B) so a row is two aligned scalar loads.
+// measured, and 1 / (2 lambda) (the background's sin(theta)/lambda from
+// |d - dir|).  12 doubles (96 B), so a row is two aligned scalar loads.
 constexpr int SRC_STRIDE = 12;
-enum { SRC_DIR = 0, SRC_LAMBDA = 3, SRC_WEIGHT = 4, SRC_E = 5, SRC_B = 8 };
+enum { SRC_DIR = 0, SRC_LAMBDA = 3, SRC_WEIGHT = 4, SRC_E = 5, SRC_B = 8, SRC_HIL = 11 };
 
 // Lower bound of |f| = |h - rint(h)| inside the binary64/32 lattice factor.
 // sin^2(pi N f)/sin^2(pi f) = N^2 (1 - (N^2-1) pi^2 f^2 / 3 + ...), so for
@@ -138,6 +139,20 @@ struct ServeArgs {
     uint64_t idle_ticks;      // 100 MHz ticks of device-wide idleness before the kernel exits
 };
 
+// Background of an amorphous scatterer over one region of interest: the
+// geometry, sources, image and normalisation of p (n_roi = 1, norm =
+// r_e^2 fluence molecules / O^2) and the scattering curve as knots
+// (stol_k, F_k, slope_k) with slope_{n-1} = 0, in binary64 and binary32.
+constexpr int BG_MAX_KNOTS = 1024;
+struct BgParams {
+    Params p;
+    const double *knots64;  // [n_knots][3]
+    const float *knots32;   // [n_knots][3]
+    const float *src32;     // [n_src][SRC_STRIDE] binary32 copies of the source rows
+    int32_t n_knots;
+    int32_t n_pad;          // smallest power of two >= n_knots
+};
+
 // Launchers (xrt_kernels.hip).  Return the hipError_t of the launch.
 // serve_blocks_per_cu: workgroups of the persistent kernel one compute unit
 // holds at once (0 on error).
@@ -153,6 +168,7 @@ hipError_t launch_grad(const Params &p, int precision, bool clamp, const void *d
 hipError_t launch_serve(const ServeArgs &a, int precision, int shape, int n_wg, hipStream_t stream);
 hipError_t launch_sinpi(const double *x, int64_t n, double *s64, float *s32, hipStream_t stream);
 hipError_t launch_exp(const double *x, int64_t n, double *y, hipStream_t stream);
+hipError_t launch_background(const BgParams &b, int precision, hipStream_t stream);
 hipError_t launch_trace(const Params &p, int64_t n, const int32_t *idx, double *S, double *h,
                         hipStream_t stream);
 

@@ -859,6 +859,115 @@ hipError_t launch_grad(const Params &p, int precision, bool clamp, const void *d
 }
 
 // ---------------------------------------------------------------------------
+// Background of an amorphous scatterer (section III's second kernel: the air
+// and water around the crystal).  Per term (sample point, source):
+// stol = |d - dir| / (2 lambda), the scattering curve F at stol, and
+// w P F^2; no spindle or mosaic loop and no table gather, so it is a short
+// VALU-bound kernel with the spots kernel's pixel layout (one pixel per lane,
+// a 16 x 16 tile per workgroup).  The curve is staged in LDS: the knot
+// abscissae padded with NaN to a power of two (a binary search of fixed
+// depth that can never step onto a pad, since NaN <= s is false), then the
+// (F_k, slope_k) pairs.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <typename R>
+__device__ __forceinline__ R bg_curve(const R *xs, const R *ym, int n_pad, R s)
+{
+    s = s < xs[0] ? xs[0] : s;  // below the first knot: F_0
+    int k = 0;                  // largest k with xs[k] <= s
+    for (int step = n_pad >> 1; step > 0; step >>= 1) k = xs[k + step] <= s ? k + step : k;
+    return fma_r(s - xs[k], ym[2 * k + 1], ym[2 * k]);  // slope 0 past the last knot
+}
+
+// Kahn factor of one source row (binary64 or binary32 copy), P =
+// (1 + c^2 - K (x^2 - y^2)) / 2 as in the spots kernel, by fused products.
+template <typename R>
+__device__ __forceinline__ R bg_polarization(const R *src, const R d[3], R K)
+{
+    const R c = fma_r(d[2], src[SRC_DIR + 2], fma_r(d[1], src[SRC_DIR + 1], d[0] * src[SRC_DIR]));
+    const R x = fma_r(d[2], src[SRC_E + 2], fma_r(d[1], src[SRC_E + 1], d[0] * src[SRC_E]));
+    const R y = fma_r(d[2], src[SRC_B + 2], fma_r(d[1], src[SRC_B + 1], d[0] * src[SRC_B]));
+    return R(0.5) * fma_r(-K, fma_r(x, x, -(y * y)), fma_r(c, c, R(1)));
+}
+
+template <int PREC>
+__global__ __launch_bounds__(BLOCK) void background_kernel(const BgParams b)
+{
+    using R = typename std::conditional<PREC == XRT_FP64, double, float>::type;
+    extern __shared__ double bg_lds[];
+    const Params &p = b.p;
+    R *xs = reinterpret_cast<R *>(bg_lds);
+    R *ym = xs + b.n_pad;
+    const R *kn;
+    if constexpr (PREC == XRT_FP64)
+        kn = b.knots64;
+    else
+        kn = b.knots32;
+    for (int i = threadIdx.x; i < b.n_pad; i += BLOCK) {
+        xs[i] = i < b.n_knots ? kn[3 * i] : R(NAN);  // never <= s, whatever s is
+        if (i < b.n_knots) {
+            ym[2 * i] = kn[3 * i + 1];
+            ym[2 * i + 1] = kn[3 * i + 2];
+        }
+    }
+    __syncthreads();
+    const Pixel px = tile_pixel(p, xcd_tile(blockIdx.x, p.n_tiles));
+    double acc64 = 0.0;
+    float acc = 0.0f, accc = 0.0f;
+    for (int u = 0; u < p.O; ++u)
+        for (int v = 0; v < p.O; ++v)
+            for (int t = 0; t < p.T; ++t) {
+                double d[3], dist;
+                sample_dir(p, px.i_f, px.i_s, u, v, t, d, dist);
+                const double wgeo = sample_weight(p, d, dist, t);
+                if constexpr (PREC == XRT_FP64) {
+                    double sub = 0.0;
+                    for (int j = 0; j < p.n_src; ++j) {
+                        const double *src = p.src + SRC_STRIDE * j;
+                        const double e0 = d[0] - src[SRC_DIR], e1 = d[1] - src[SRC_DIR + 1],
+                                     e2 = d[2] - src[SRC_DIR + 2];
+                        const double len = __builtin_sqrt(__builtin_fma(e2, e2, __builtin_fma(e1, e1, e0 * e0)));
+                        const double F = bg_curve(xs, ym, b.n_pad, len * src[SRC_HIL]);
+                        const double P = bg_polarization(src, d, p.kahn);
+                        sub = __builtin_fma(src[SRC_WEIGHT] * P, F * F, sub);
+                    }
+                    acc64 = __builtin_fma(wgeo, sub, acc64);
+                } else {
+                    // d - dir in binary64 (it cancels near the direct beam),
+                    // everything after it in binary32
+                    const float d32[3] = {(float)d[0], (float)d[1], (float)d[2]};
+                    float s = 0.0f, c = 0.0f;
+                    for (int j = 0; j < p.n_src; ++j) {
+                        const double *src = p.src + SRC_STRIDE * j;
+                        const float *src32 = b.src32 + SRC_STRIDE * j;
+                        const float e0 = (float)(d[0] - src[SRC_DIR]), e1 = (float)(d[1] - src[SRC_DIR + 1]),
+                                    e2 = (float)(d[2] - src[SRC_DIR + 2]);
+                        const float len = __builtin_sqrtf(__builtin_fmaf(e2, e2, __builtin_fmaf(e1, e1, e0 * e0)));
+                        const float F = bg_curve(xs, ym, b.n_pad, len * src32[SRC_HIL]);
+                        const float P = bg_polarization(src32, d32, (float)p.kahn);
+                        kahn_add(s, c, src32[SRC_WEIGHT] * P * (F * F));
+                    }
+                    kahn_add(acc, accc, (float)wgeo * (s - c));
+                }
+            }
+    const double sum = PREC == XRT_FP64 ? acc64 : (double)(acc - accc);
+    if (px.live) store_pixel(p, px.out, p.norm * sum);
+}
+
+hipError_t launch_background(const BgParams &b, int precision, hipStream_t stream)
+{
+    const dim3 grid(b.p.n_tiles), block(BLOCK);
+    const size_t n = (size_t)b.n_pad + 2 * (size_t)b.n_knots;
+    if (precision == XRT_FP64)
+        hipLaunchKernelGGL(background_kernel<XRT_FP64>, grid, block, n * sizeof(double), stream, b);
+    else
+        hipLaunchKernelGGL(background_kernel<XRT_MIXED>, grid, block, n * sizeof(float), stream, b);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Padded F^2 tables: entry (a, b, c) of the (na+2P)(nb+2P)(nc+2P) box holds
 // F(a-P, b-P, c-P)^2 inside the tabulated range and F_default^2 elsewhere.
 // ---------------------------------------------------------------------------

@@ -68,6 +68,13 @@ class FhklDesc(C.Structure):
     ]
 
 
+class BackgroundDesc(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("n_knots", C.c_int32),
+        ("stol", _pd), ("F", _pd), ("molecules", C.c_double),
+    ]
+
+
 class ServerDesc(C.Structure):
     _fields_ = [
         ("struct_size", C.c_uint32), ("hbm_budget", C.c_uint64), ("max_resident", C.c_int32),
@@ -96,7 +103,8 @@ _lib = None
 SYMBOLS = ("xrt_version", "xrt_last_error", "xrt_fhkl_create", "xrt_fhkl_destroy",
            "xrt_simulate", "xrt_simulate_rois", "xrt_backward_rois", "xrt_server_create",
            "xrt_server_destroy", "xrt_server_submit", "xrt_server_progress", "xrt_server_info",
-           "xrt_server_image", "xrt_server_release", "xrt_server_cancel", "xrt_cell_mats", "xrt_trace_terms", "xrt_sinpi", "xrt_exp")
+           "xrt_server_image", "xrt_server_release", "xrt_server_cancel", "xrt_cell_mats", "xrt_trace_terms", "xrt_sinpi", "xrt_exp",
+           "xrt_simulate_background")
 XRT_SHOT_QUEUED, XRT_SHOT_RUNNING, XRT_SHOT_DONE = 0, 1, 2
 
 
@@ -120,6 +128,8 @@ def load():
     lib.xrt_backward_rois.argtypes = [C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal), C.c_void_p,
                                       C.c_int32, C.c_int64, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                       C.c_int32, C.c_void_p, C.c_void_p]
+    lib.xrt_simulate_background.argtypes = [C.POINTER(Detector), C.POINTER(Beam), C.POINTER(BackgroundDesc),
+                                            C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
     lib.xrt_server_create.argtypes = [C.POINTER(ServerDesc), C.c_void_p, C.POINTER(C.c_void_p)]
     lib.xrt_server_destroy.argtypes = [C.c_void_p]
     lib.xrt_server_submit.argtypes = [C.c_void_p, C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal),
@@ -159,21 +169,25 @@ def _arr(x, dtype=np.float64):
 class ShotStructs:
     """The three C structs of one shot plus the host arrays they point to."""
 
-    def __init__(self, shot, roi=None):
+    def __init__(self, shot, roi=None, crystal=True):
         f0, f1, s0, s1 = shot.roi if roi is None else roi
         self.det = Detector(
             C.sizeof(Detector), shot.n_fast, shot.n_slow, shot.pixel, shot.distance,
             shot.beam_f, shot.beam_s, _d3(*shot.fdet), _d3(*shot.sdet), _d3(*shot.odet),
             shot.oversample, shot.n_layers, shot.layer_dt, shot.atten_len, f0, f1, s0, s1)
-        self._keep = [_arr(shot.src_dir), _arr(shot.src_lambda), _arr(shot.src_weight), _arr(shot.umats)]
-        sd, sl, sw, um = self._keep
+        self._keep = [_arr(shot.src_dir), _arr(shot.src_lambda), _arr(shot.src_weight)]
+        sd, sl, sw = self._keep
         self.beam = Beam(C.sizeof(Beam), len(sl), sd.ctypes.data_as(_pd), sl.ctypes.data_as(_pd),
                          sw.ctypes.data_as(_pd), shot.fluence, shot.kahn, _d3(*shot.evec))
+        self.roi_shape = (s1 - s0, f1 - f0)
+        if not crystal:
+            return
+        um = _arr(shot.umats)
+        self._keep.append(um)
         self.xtal = Crystal(
             C.sizeof(Crystal), _d9(*_arr(shot.cell).ravel()), _d9(*_arr(shot.U).ravel()),
             um.shape[0], um.ctypes.data_as(_pd), shot.n_phi, shot.phi0, shot.dphi,
             _d3(*shot.spindle), _d3(*shot.N), int(shot.shape), shot.gauss_c, shot.scale)
-        self.roi_shape = (s1 - s0, f1 - f0)
 
 
 class Fhkl:
@@ -244,14 +258,37 @@ def simulate(shot, fhkl: Fhkl, precision="fp64", out=None, out_dtype=None, accum
     return out
 
 
+def simulate_background(shot, bg, precision="fp64", out=None, out_dtype=None, accumulate=False,
+                        stream=None, roi=None):
+    """Enqueue xrt_simulate_background: the background of an amorphous
+    scatterer ``bg`` (attributes ``stol``, ``F``, ``molecules``, as
+    ``synth.Background``) over the detector and beam of ``shot`` (its crystal
+    is not used); returns the image tensor (allocated if ``out`` is None)."""
+    import torch
+    st = ShotStructs(shot, roi, crystal=False)
+    if out is None:
+        if out_dtype is None:
+            out_dtype = torch.float64 if precision == "fp64" else torch.float32
+        out = torch.zeros(st.roi_shape, dtype=out_dtype, device="cuda")
+    if tuple(out.shape) != st.roi_shape or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError(f"out must be a contiguous GPU tensor of shape {st.roi_shape}")
+    x, F = _arr(bg.stol), _arr(bg.F)
+    if x.shape != F.shape or x.ndim != 1:
+        raise ValueError("stol and F must be 1-D arrays of equal length")
+    d = BackgroundDesc(C.sizeof(BackgroundDesc), len(x), x.ctypes.data_as(_pd), F.ctypes.data_as(_pd),
+                       float(bg.molecules))
+    _check(load().xrt_simulate_background(C.byref(st.det), C.byref(st.beam), C.byref(d), _PREC[precision],
+                                          C.c_void_p(out.data_ptr()), _dtype_code(out),
+                                          int(bool(accumulate)), _stream(stream)))
+    return out
+
+
 def _origins(origins):
     o = _arr(origins, np.int32)
     if o.ndim != 2 or o.shape[1] != 2:
         raise ValueError("origins must be (n_roi, 2) int32 (i_f, i_s)")
     return o
 
-
-_DT = {}
 
 
 def _dtype_code(t):

@@ -112,6 +112,47 @@ def test_call_validation():
     assert _call_simulate(st, image=0) == xrt.XRT_EINVAL
 
 
+def _call_background(shot, stol, F, molecules=1.0e10, n=None, size=None, image=1, precision=0, acc=0):
+    st = xrt.ShotStructs(shot, crystal=False)
+    x, f = np.ascontiguousarray(stol, np.float64), np.ascontiguousarray(F, np.float64)
+    d = xrt.BackgroundDesc(C.sizeof(xrt.BackgroundDesc) if size is None else size,
+                           len(x) if n is None else n, x.ctypes.data_as(xrt._pd), f.ctypes.data_as(xrt._pd),
+                           molecules)
+    return xrt.load().xrt_simulate_background(C.byref(st.det), C.byref(st.beam), C.byref(d), precision,
+                                              C.c_void_p(image), 0, acc, None)
+
+
+def test_background_validation():
+    """Every malformed curve is rejected on the host, before anything is
+    enqueued."""
+    shot = synth.tiny_shot()
+    bg = synth.water_background()
+    x, F = bg.stol, bg.F
+    cases = [
+        (dict(stol=x[:1], F=F[:1]), xrt.XRT_ERANGE),                       # one knot
+        (dict(stol=np.linspace(0, 1, 1025), F=np.ones(1025)), xrt.XRT_ERANGE),
+        (dict(stol=x[::-1].copy(), F=F), xrt.XRT_EINVAL),                  # decreasing
+        (dict(stol=np.r_[x[:3], x[2:]], F=np.r_[F[:3], F[2:]]), xrt.XRT_EINVAL),  # repeated knot
+        (dict(stol=x, F=np.r_[F[:-1], np.nan]), xrt.XRT_EINVAL),
+        (dict(stol=x, F=F, molecules=-1.0), xrt.XRT_EINVAL),
+        (dict(stol=x, F=F, molecules=float("inf")), xrt.XRT_EINVAL),
+        (dict(stol=np.array([0.0, 1e-300]), F=np.array([0.0, 1.0])), xrt.XRT_EINVAL),  # slope overflows
+        (dict(stol=np.array([0.0, 1e39]), F=np.array([0.0, 1.0])), xrt.XRT_ERANGE),    # not binary32
+        (dict(stol=x, F=F, size=8), xrt.XRT_EVERSION),
+        (dict(stol=x, F=F, image=0), xrt.XRT_EINVAL),
+        (dict(stol=x, F=F, precision=3), xrt.XRT_EINVAL),
+        (dict(stol=x, F=F, acc=2), xrt.XRT_EINVAL),
+    ]
+    for kw, code in cases:
+        assert _call_background(shot, **kw) == code, (kw, err())
+        assert err()
+    st = xrt.ShotStructs(shot, crystal=False)
+    assert xrt.load().xrt_simulate_background(C.byref(st.det), C.byref(st.beam), None, 0, C.c_void_p(1), 0, 0,
+                                              None) == xrt.XRT_EINVAL
+    bad = shot.replace(roi=(0, 129, 0, 128))
+    assert _call_background(bad, x, F) == xrt.XRT_EINVAL
+
+
 def test_fhkl_create_validation():
     lib = xrt.load()
     h = C.c_void_p()
