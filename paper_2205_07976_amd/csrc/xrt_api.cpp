@@ -743,8 +743,6 @@ xrt_status xrt_simulate_background(const xrt_detector *det, const xrt_beam *beam
     p.out_f64 = out_dtype == XRT_F64;
     p.accumulate = accumulate;
     b.n_knots = n;
-    b.n_pad = 1;
-    while (b.n_pad < n) b.n_pad *= 2;
 
     hipStream_t s = (hipStream_t)stream;
     double *tables = nullptr;

@@ -150,7 +150,7 @@ struct BgParams {
     const float *knots32;   // [n_knots][3]
     const float *src32;     // [n_src][SRC_STRIDE] binary32 copies of the source rows
     int32_t n_knots;
-    int32_t n_pad;          // smallest power of two >= n_knots
+    int32_t pad;
 };
 
 // Launchers (xrt_kernels.hip).  Return the hipError_t of the launch.

@@ -864,21 +864,46 @@ hipError_t launch_grad(const Params &p, int precision, bool clamp, const void *d
 // stol = |d - dir| / (2 lambda), the scattering curve F at stol, and
 // w P F^2; no spindle or mosaic loop and no table gather, so it is a short
 // VALU-bound kernel with the spots kernel's pixel layout (one pixel per lane,
-// a 16 x 16 tile per workgroup).  The curve is staged in LDS: the knot
-// abscissae padded with NaN to a power of two (a binary search of fixed
-// depth that can never step onto a pad, since NaN <= s is false), then the
-// (F_k, slope_k) pairs.
+// a 16 x 16 tile per workgroup).  The curve is staged in LDS: the n knot
+// abscissae and one NaN after them, then the (F_k, slope_k) pairs.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double max_r(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ float max_r(float a, float b) { return __builtin_fmaxf(a, b); }
 
-template <typename R>
-__device__ __forceinline__ R bg_curve(const R *xs, const R *ym, int n_pad, R s)
+// |d - dir| from its square x in [0, 4] (unit vectors), within an ulp or two
+// rather than correctly rounded (the curve is continuous, so this moves F by
+// as little).  binary64: the hardware reciprocal square root y of
+// x + 2^-1000 (the bias keeps x = 0 finite and is far below half an ulp of
+// any nonzero x met here), one Goldschmidt step on (x y, y / 2) and one
+// Newton correction of the root.  binary32: the hardware square root.
+__device__ __forceinline__ double root_small(double x)
 {
-    s = s < xs[0] ? xs[0] : s;  // below the first knot: F_0
-    int k = 0;                  // largest k with xs[k] <= s
-    for (int step = n_pad >> 1; step > 0; step >>= 1) k = xs[k + step] <= s ? k + step : k;
-    return fma_r(s - xs[k], ym[2 * k + 1], ym[2 * k]);  // slope 0 past the last knot
+    x += 0x1p-1000;
+    const double y = __builtin_amdgcn_rsq(x);
+    double s = x * y, h = 0.5 * y;
+    const double r = __builtin_fma(-h, s, 0.5);
+    s = __builtin_fma(s, r, s);
+    h = __builtin_fma(h, r, h);
+    return __builtin_fma(__builtin_fma(-s, s, x), h, s);
+}
+__device__ __forceinline__ float root_small(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// The curve at s, with k the lane's interval from its previous term: walk
+// down while the knot is above s, then up while the next knot is at or below
+// s.  Successive terms of a pixel (sources of nearby wavelength, neighbouring
+// sub-pixels) nearly always stay in the same interval, so a lookup is two
+// LDS reads and two compares.  s is clamped to the first knot, so the
+// downward walk stops at 0; the NaN after the last knot compares false, so
+// the upward walk stops at n - 1 (whose slope is 0: constant beyond it).
+template <typename R>
+__device__ __forceinline__ R bg_curve(const R *xs, const R *ym, int &k, R s)
+{
+    s = max_r(s, xs[0]);  // a NaN s becomes the first knot
+    while (xs[k] > s) --k;
+    while (xs[k + 1] <= s) ++k;
+    return fma_r(s - xs[k], ym[2 * k + 1], ym[2 * k]);
 }
 
 // Kahn factor of one source row (binary64 or binary32 copy), P =
@@ -893,20 +918,20 @@ __device__ __forceinline__ R bg_polarization(const R *src, const R d[3], R K)
 }
 
 template <int PREC>
-__global__ __launch_bounds__(BLOCK) void background_kernel(const BgParams b)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void background_kernel(const BgParams b)
 {
     using R = typename std::conditional<PREC == XRT_FP64, double, float>::type;
     extern __shared__ double bg_lds[];
     const Params &p = b.p;
-    R *xs = reinterpret_cast<R *>(bg_lds);
-    R *ym = xs + b.n_pad;
+    R *xs = reinterpret_cast<R *>(bg_lds);  // [n + 1]
+    R *ym = xs + b.n_knots + 1;              // [n][2]
     const R *kn;
     if constexpr (PREC == XRT_FP64)
         kn = b.knots64;
     else
         kn = b.knots32;
-    for (int i = threadIdx.x; i < b.n_pad; i += BLOCK) {
-        xs[i] = i < b.n_knots ? kn[3 * i] : R(NAN);  // never <= s, whatever s is
+    for (int i = threadIdx.x; i <= b.n_knots; i += BLOCK) {
+        xs[i] = i < b.n_knots ? kn[3 * i] : R(NAN);
         if (i < b.n_knots) {
             ym[2 * i] = kn[3 * i + 1];
             ym[2 * i + 1] = kn[3 * i + 2];
@@ -914,6 +939,7 @@ __global__ __launch_bounds__(BLOCK) void background_kernel(const BgParams b)
     }
     __syncthreads();
     const Pixel px = tile_pixel(p, xcd_tile(blockIdx.x, p.n_tiles));
+    int k = 0;  // interval of the previous term
     double acc64 = 0.0;
     float acc = 0.0f, accc = 0.0f;
     for (int u = 0; u < p.O; ++u)
@@ -928,8 +954,8 @@ __global__ __launch_bounds__(BLOCK) void background_kernel(const BgParams b)
                         const double *src = p.src + SRC_STRIDE * j;
                         const double e0 = d[0] - src[SRC_DIR], e1 = d[1] - src[SRC_DIR + 1],
                                      e2 = d[2] - src[SRC_DIR + 2];
-                        const double len = __builtin_sqrt(__builtin_fma(e2, e2, __builtin_fma(e1, e1, e0 * e0)));
-                        const double F = bg_curve(xs, ym, b.n_pad, len * src[SRC_HIL]);
+                        const double len = root_small(__builtin_fma(e2, e2, __builtin_fma(e1, e1, e0 * e0)));
+                        const double F = bg_curve(xs, ym, k, len * src[SRC_HIL]);
                         const double P = bg_polarization(src, d, p.kahn);
                         sub = __builtin_fma(src[SRC_WEIGHT] * P, F * F, sub);
                     }
@@ -944,8 +970,8 @@ __global__ __launch_bounds__(BLOCK) void background_kernel(const BgParams b)
                         const float *src32 = b.src32 + SRC_STRIDE * j;
                         const float e0 = (float)(d[0] - src[SRC_DIR]), e1 = (float)(d[1] - src[SRC_DIR + 1]),
                                     e2 = (float)(d[2] - src[SRC_DIR + 2]);
-                        const float len = __builtin_sqrtf(__builtin_fmaf(e2, e2, __builtin_fmaf(e1, e1, e0 * e0)));
-                        const float F = bg_curve(xs, ym, b.n_pad, len * src32[SRC_HIL]);
+                        const float len = root_small(__builtin_fmaf(e2, e2, __builtin_fmaf(e1, e1, e0 * e0)));
+                        const float F = bg_curve(xs, ym, k, len * src32[SRC_HIL]);
                         const float P = bg_polarization(src32, d32, (float)p.kahn);
                         kahn_add(s, c, src32[SRC_WEIGHT] * P * (F * F));
                     }
@@ -959,7 +985,7 @@ __global__ __launch_bounds__(BLOCK) void background_kernel(const BgParams b)
 hipError_t launch_background(const BgParams &b, int precision, hipStream_t stream)
 {
     const dim3 grid(b.p.n_tiles), block(BLOCK);
-    const size_t n = (size_t)b.n_pad + 2 * (size_t)b.n_knots;
+    const size_t n = 3 * (size_t)b.n_knots + 1;
     if (precision == XRT_FP64)
         hipLaunchKernelGGL(background_kernel<XRT_FP64>, grid, block, n * sizeof(double), stream, b);
     else

@@ -134,10 +134,10 @@ def smooth(s):
 @pytest.mark.parametrize("kind", ["two_knots", "short_range", "pad_33", "max_1024"])
 def test_curve_edge_cases(precision, kind):
     """Two knots (a single line); a curve ending far below the detector's
-    largest stol (constant extension over most pixels); 33 knots (31 NaN
-    pads in the search); the largest accepted curve, 1024 knots (the deepest
-    search).  Smooth curves (condition number below 10), so the plain
-    tolerances hold."""
+    largest stol (constant extension over most pixels); 33 knots; the
+    largest accepted curve, 1024 knots (intervals a few pixels wide, so the
+    interval walk moves often).  Smooth curves (condition number below 10),
+    so the plain tolerances hold."""
     shot = synth.tiny_shot().replace(distance=0.03, kahn=0.5)  # 2theta up to ~17 degrees
     rng = np.random.default_rng(4)
     if kind == "two_knots":
