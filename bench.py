@@ -5,7 +5,8 @@ layers x 100 sources x 50 mosaic domains = 3.7344e11 pixel terms, binary64,
 inputs (tables, structure factors) resident on the device; the step is the
 xrt_simulate call (small table upload + the spots kernel).  The same shot is
 also timed in the mixed-precision form and its error against the oracle on
-sampled pixels is reported beside it.
+sampled pixels is reported beside it; so is the background of a water-like
+scatterer over the same detector.
 
 Prints one JSON line.  Synthetic, seeded inputs (synth.full_shot).
 """
@@ -33,6 +34,18 @@ if ROOT not in sys.path:
 #             Kahan 4; table offset 3 binary64 FMA
 #             -> 24 + 84 + 4 + 5 + 2 + 4 + 6 = 129
 C_ALG = {"fp64": 204, "mixed": 129}
+# The background of an amorphous scatterer, per (pixel, sub-pixel, layer,
+# source) term, same units:
+#   binary64: d - dir 3 subs, |d - dir|^2 3 ops, its root (reciprocal square
+#             root 8 + 5 ops), times 1/(2 lambda) 1, clamp to the first knot 1,
+#             interval test 2 compares, interpolation 2, F^2 1, Kahn factor
+#             (3 dot products 9 + 5), w P 1, accumulate 1
+#             -> 6 + 6 + 18 + 2 + 2 + 4 + 4 + 2 + 28 + 4 = 76
+#   mixed:    d - dir 3 binary64 subs and 3 conversions (12); then binary32:
+#             square 3, root 4, scale 1, clamp 1, compares 2, interpolation 2,
+#             F^2 1, Kahn factor 14, products 2, Kahan add 4
+#             -> 12 + 3 + 4 + 1 + 1 + 2 + 2 + 1 + 14 + 2 + 4 = 46
+C_ALG_BG = {"fp64": 76, "mixed": 46}
 # MI355X binary32 VALU peak: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz
 # = 78.64 T lane-op/s (157.3 TFLOP/s counting an FMA as 2 flops)
 PEAK_OPS = 256 * 4 * 32 * 2.4e9
@@ -83,6 +96,51 @@ def cpu_baseline(shot, budget_s=15.0):
     terms = n * shot.terms_per_pixel
     return {"value": terms / dt / 1e9, "unit": "Gterm/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} seeded pixels of the full-size shot ({terms:.3e} terms, {dt:.1f} s)"}
+
+
+def background_bench(shot, steps):
+    """The background of the water-like scatterer over the full-size detector
+    (1200 terms per pixel: no spindle or mosaic loop), both precisions, timed
+    with HIP events around each call on the current stream; a sampled check
+    against the oracle; the oracle's own rate on a pixel subset."""
+    import numpy as np
+    import torch
+    import synth
+    from oracle import oracle as o
+    from paper_2205_07976_amd import xrt
+    bg = synth.water_background()
+    terms = shot.n_pixels * shot.oversample ** 2 * shot.n_layers * shot.n_src
+    out = {"workload": f"water-like curve ({bg.n_knots} knots) over the full-size detector: "
+                       "2463x2527 px, oversample 2, 3 layers, 100 sources = 1200 terms/px",
+           "terms": terms, "c_alg_per_term": C_ALG_BG, "peak": PEAK_OPS / 1e12,
+           "unit": "T fp32-lane-op/s"}
+    pix = synth.pixel_sample(shot, 256, 77)
+    ref = o.background(shot, bg, pix, nthreads=min(16, os.cpu_count() or 1))
+    n = max(steps, 5)
+    for prec in ("fp64", "mixed"):
+        img = torch.empty(shot.roi_shape, dtype=torch.float64 if prec == "fp64" else torch.float32, device="cuda")
+        xrt.simulate_background(shot, bg, precision=prec, out=img)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for a, b in evs:
+            a.record()
+            xrt.simulate_background(shot, bg, precision=prec, out=img)
+            b.record()
+        torch.cuda.synchronize()
+        ms = sum(a.elapsed_time(b) for a, b in evs) / n
+        x = img.cpu().numpy()[pix[:, 1], pix[:, 0]].astype(np.float64)
+        ach = C_ALG_BG[prec] * terms / (ms * 1e-3)
+        out[prec] = {"ms": ms, "Gterm_s": terms / ms / 1e6, "achieved": ach / 1e12, "frac": ach / PEAK_OPS,
+                     "max_rel_err": float(np.max(np.abs(x - ref) / ref)), "err_sample": "256 seeded pixels"}
+        log(f"background {prec}: {ms:.2f} ms, {terms / ms / 1e6:.0f} Gterm/s, frac {ach / PEAK_OPS:.3f}")
+    cores = min(16, os.cpu_count() or 1)
+    sample = synth.pixel_sample(shot, 262144, 78)
+    t0 = time.perf_counter()
+    o.background(shot, bg, sample, nthreads=cores)
+    dt = time.perf_counter() - t0
+    out["cpu_oracle"] = {"Gterm_s": len(sample) * 1200 / dt / 1e9, "cores": cores,
+                         "sample": f"{len(sample)} seeded pixels ({dt:.2f} s)"}
+    return out
 
 
 def mixed_error(shot, img32):
@@ -230,6 +288,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the regions-of-interest adjoint")
+    ap.add_argument("--no-background", action="store_true", help="skip the background of an amorphous scatterer")
     ap.add_argument("--no-serve", action="store_true", help="skip the served shot stream")
     ap.add_argument("--serve-sweep", action="store_true",
                     help="also serve 1000 Poisson shots at 0.5, 0.8 and 0.95 x capacity and measure the "
@@ -294,6 +353,10 @@ def main():
         ms_s = sum(ev_s) / len(ev_s)
         res["small_roi"][prec] = {"ms": ms_s, "Gterm_s": small.n_terms / ms_s / 1e6}
         log(f"small ROI {prec}: {ms_s:.2f} ms, {small.n_terms / ms_s / 1e6:.0f} Gterm/s")
+
+    if not args.no_background:
+        res["background"] = background_bench(shot, args.steps)
+        res["background"]["image_fp64_ms"] = kern_ms + res["background"]["fp64"]["ms"]
 
     if not args.no_adjoint:
         res["adjoint"] = adjoint_bench(args.steps)
