@@ -864,8 +864,9 @@ hipError_t launch_grad(const Params &p, int precision, bool clamp, const void *d
 // stol = |d - dir| / (2 lambda), the scattering curve F at stol, and
 // w P F^2; no spindle or mosaic loop and no table gather, so it is a short
 // VALU-bound kernel with the spots kernel's pixel layout (one pixel per lane,
-// a 16 x 16 tile per workgroup).  The curve is staged in LDS: the n knot
-// abscissae and one NaN after them, then the (F_k, slope_k) pairs.
+// a 16 x 16 tile per workgroup).  The curve is staged in LDS as one record
+// per interval.  The source loop is unrolled by two, so the scalar loads of
+// the next source row overlap the current term.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -890,20 +891,27 @@ __device__ __forceinline__ double root_small(double x)
 }
 __device__ __forceinline__ float root_small(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// One interval of the curve in LDS: its knot, the next knot (NaN after the
+// last), F and the slope (0 after the last knot: constant beyond it).
+template <typename R>
+struct alignas(4 * sizeof(R)) BgKnot {
+    R x, xn, y, m;
+};
 // The curve at s, with k the lane's interval from its previous term: walk
 // down while the knot is above s, then up while the next knot is at or below
 // s.  Successive terms of a pixel (sources of nearby wavelength, neighbouring
-// sub-pixels) nearly always stay in the same interval, so a lookup is two
-// LDS reads and two compares.  s is clamped to the first knot, so the
+// sub-pixels) nearly always stay in the same interval, so a lookup is one LDS
+// read of a record and two compares.  s is clamped to the first knot, so the
 // downward walk stops at 0; the NaN after the last knot compares false, so
-// the upward walk stops at n - 1 (whose slope is 0: constant beyond it).
+// the upward walk stops at n - 1.
 template <typename R>
-__device__ __forceinline__ R bg_curve(const R *xs, const R *ym, int &k, R s)
+__device__ __forceinline__ R bg_curve(const BgKnot<R> *kt, int &k, R s)
 {
-    s = max_r(s, xs[0]);  // a NaN s becomes the first knot
-    while (xs[k] > s) --k;
-    while (xs[k + 1] <= s) ++k;
-    return fma_r(s - xs[k], ym[2 * k + 1], ym[2 * k]);
+    s = max_r(s, kt[0].x);
+    BgKnot<R> c = kt[k];
+    while (c.x > s) c = kt[--k];
+    while (c.xn <= s) c = kt[++k];
+    return fma_r(s - c.x, c.m, c.y);
 }
 
 // Kahn factor of one source row (binary64 or binary32 copy), P =
@@ -923,19 +931,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
     using R = typename std::conditional<PREC == XRT_FP64, double, float>::type;
     extern __shared__ double bg_lds[];
     const Params &p = b.p;
-    R *xs = reinterpret_cast<R *>(bg_lds);  // [n + 1]
-    R *ym = xs + b.n_knots + 1;              // [n][2]
+    BgKnot<R> *kt = reinterpret_cast<BgKnot<R> *>(bg_lds);  // [n]
     const R *kn;
     if constexpr (PREC == XRT_FP64)
         kn = b.knots64;
     else
         kn = b.knots32;
-    for (int i = threadIdx.x; i <= b.n_knots; i += BLOCK) {
-        xs[i] = i < b.n_knots ? kn[3 * i] : R(NAN);
-        if (i < b.n_knots) {
-            ym[2 * i] = kn[3 * i + 1];
-            ym[2 * i + 1] = kn[3 * i + 2];
-        }
+    for (int i = threadIdx.x; i < b.n_knots; i += BLOCK) {
+        BgKnot<R> c;
+        c.x = kn[3 * i];
+        c.xn = i + 1 < b.n_knots ? kn[3 * i + 3] : R(NAN);
+        c.y = kn[3 * i + 1];
+        c.m = kn[3 * i + 2];
+        kt[i] = c;
     }
     __syncthreads();
     const Pixel px = tile_pixel(p, xcd_tile(blockIdx.x, p.n_tiles));
@@ -950,12 +958,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
                 const double wgeo = sample_weight(p, d, dist, t);
                 if constexpr (PREC == XRT_FP64) {
                     double sub = 0.0;
+#pragma unroll 2
                     for (int j = 0; j < p.n_src; ++j) {
                         const double *src = p.src + SRC_STRIDE * j;
                         const double e0 = d[0] - src[SRC_DIR], e1 = d[1] - src[SRC_DIR + 1],
                                      e2 = d[2] - src[SRC_DIR + 2];
                         const double len = root_small(__builtin_fma(e2, e2, __builtin_fma(e1, e1, e0 * e0)));
-                        const double F = bg_curve(xs, ym, k, len * src[SRC_HIL]);
+                        const double F = bg_curve(kt, k, len * src[SRC_HIL]);
                         const double P = bg_polarization(src, d, p.kahn);
                         sub = __builtin_fma(src[SRC_WEIGHT] * P, F * F, sub);
                     }
@@ -965,13 +974,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
                     // everything after it in binary32
                     const float d32[3] = {(float)d[0], (float)d[1], (float)d[2]};
                     float s = 0.0f, c = 0.0f;
+#pragma unroll 2
                     for (int j = 0; j < p.n_src; ++j) {
                         const double *src = p.src + SRC_STRIDE * j;
                         const float *src32 = b.src32 + SRC_STRIDE * j;
                         const float e0 = (float)(d[0] - src[SRC_DIR]), e1 = (float)(d[1] - src[SRC_DIR + 1]),
                                     e2 = (float)(d[2] - src[SRC_DIR + 2]);
                         const float len = root_small(__builtin_fmaf(e2, e2, __builtin_fmaf(e1, e1, e0 * e0)));
-                        const float F = bg_curve(xs, ym, k, len * src32[SRC_HIL]);
+                        const float F = bg_curve(kt, k, len * src32[SRC_HIL]);
                         const float P = bg_polarization(src32, d32, (float)p.kahn);
                         kahn_add(s, c, src32[SRC_WEIGHT] * P * (F * F));
                     }
@@ -985,7 +995,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
 hipError_t launch_background(const BgParams &b, int precision, hipStream_t stream)
 {
     const dim3 grid(b.p.n_tiles), block(BLOCK);
-    const size_t n = 3 * (size_t)b.n_knots + 1;
+    const size_t n = 4 * (size_t)b.n_knots;
     if (precision == XRT_FP64)
         hipLaunchKernelGGL(background_kernel<XRT_FP64>, grid, block, n * sizeof(double), stream, b);
     else
