@@ -46,6 +46,23 @@ C_ALG = {"fp64": 204, "mixed": 129}
 #             F^2 1, Kahn factor 14, products 2, Kahan add 4
 #             -> 12 + 3 + 4 + 1 + 1 + 2 + 2 + 1 + 14 + 2 + 4 = 46
 C_ALG_BG = {"fp64": 76, "mixed": 46}
+# The refinement step (Gaussian shape), per pixel term, same units:
+#   forward binary64: h 12 ops, per axis rint, sub, square, FMA (12 ops), exp
+#             (clamp, scale, rint, 2 reduction FMAs, 11 Horner FMAs, ldexp,
+#             conversion: 18 ops), table offset 3 FMAs, F^2 L^2 and the
+#             accumulate 2 -> 24 + 24 + 36 + 6 + 4 = 94
+#   forward mixed: h 12 and the axes 12 binary64 ops (48), exponent add and
+#             conversion 4, binary32 exp 5, table offset 6, product 1, Kahan 4
+#             -> 48 + 4 + 5 + 6 + 1 + 4 = 68
+#   adjoint binary64: S' = Q^T S 9 ops, h 9, axes 12, table offset 3, exp 18,
+#             two products, per axis the h derivative (2 products, 3 FMAs) and
+#             the N derivative (product, 2 FMAs), dL/dscale 1
+#             -> 18 + 18 + 24 + 6 + 36 + 4 + 48 + 2 = 156
+#   adjoint mixed: S' 9 binary64 ops and 3 conversions (24), h 9 binary64 (18),
+#             per axis rint and sub in binary64, a conversion, square and FMA
+#             (24), table offset 6, binary32 exp and 2 products 7, derivatives
+#             24 binary32 ops, dL/dscale 1 -> 24 + 18 + 24 + 6 + 7 + 24 + 1 = 104
+C_ALG_REFINE = {"fwd": {"fp64": 94, "mixed": 68}, "bwd": {"fp64": 156, "mixed": 104}}
 # MI355X binary32 VALU peak: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz
 # = 78.64 T lane-op/s (157.3 TFLOP/s counting an FMA as 2 flops)
 PEAK_OPS = 256 * 4 * 32 * 2.4e9
@@ -178,7 +195,7 @@ def adjoint_bench(steps):
     base = shot.replace(U=np.eye(3), cell=(shot.U @ shot.cell.T).T.copy())
     terms = len(origins) * size[0] * size[1] * shot.terms_per_pixel
     out = {"workload": "512 ROIs of 32x32 px around predicted spots, Gaussian N=20, 60000 terms/px",
-           "terms_per_pass": terms}
+           "terms_per_pass": terms, "c_alg_per_term": C_ALG_REFINE}
     grads = {}
     for prec in ("fp64", "mixed"):
         img = xrt.simulate_rois(base, fh, origins, size, precision=prec, out_dtype=torch.float64)
@@ -200,8 +217,11 @@ def adjoint_bench(steps):
         grads[prec] = g.cpu().numpy()
         out[prec] = {"fwd_ms": fms, "bwd_ms": bms, "fwd_Gterm_s": terms / fms / 1e6,
                      "bwd_Gterm_s": terms / bms / 1e6,
+                     "fwd_frac": C_ALG_REFINE["fwd"][prec] * terms / (fms * 1e-3) / PEAK_OPS,
+                     "bwd_frac": C_ALG_REFINE["bwd"][prec] * terms / (bms * 1e-3) / PEAK_OPS,
                      "loss": float(((img - target) ** 2).sum())}
-        log(f"adjoint {prec}: forward {fms:.1f} ms, backward {bms:.1f} ms")
+        log(f"adjoint {prec}: forward {fms:.1f} ms (frac {out[prec]['fwd_frac']:.3f}), "
+            f"backward {bms:.1f} ms (frac {out[prec]['bwd_frac']:.3f})")
     d = np.abs(grads["mixed"] - grads["fp64"])
     out["grad_fp64"] = grads["fp64"].tolist()
     out["mixed_vs_fp64_max_diff_over_max"] = [float(d[sl].max() / np.abs(grads["fp64"][sl]).max())
