@@ -261,6 +261,23 @@ xrt_status xrt_simulate_background(const xrt_detector *det, const xrt_beam *beam
                                    void *dev_image, int32_t out_dtype, int32_t accumulate,
                                    void *stream);
 
+/* Ensemble sum: add a region image into a binary64 accumulator (section III's
+ * third kernel adds the results of the other two into one binary64 image; the
+ * paper's runs then reduce the images of many shots).  For every pixel (c, r)
+ * of the image, acc[s0 + r][f0 + c] += (double) img[r][c].
+ *  dev_acc     device, [acc_ns][acc_nf] binary64, updated in place.
+ *  dev_img     device, [img_ns][img_nf] of img_dtype (XRT_F32 or XRT_F64),
+ *              e.g. a served shot's image read in place.
+ *  f0, s0      where the image's first pixel lands; the image must lie inside
+ *              the accumulator.
+ * One kernel on `stream`; calls on one stream add in call order, so an
+ * ensemble summed in a fixed order gives the same bits every time.  The
+ * image and the accumulator must not overlap.
+ * Errors: EINVAL (NULL, dtype, sizes, placement), ERANGE, EDEVICE. */
+xrt_status xrt_add_image(double *dev_acc, int32_t acc_nf, int32_t acc_ns, const void *dev_img,
+                         int32_t img_dtype, int32_t img_nf, int32_t img_ns, int32_t f0, int32_t s0,
+                         void *stream);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of independent shots on one device.
  *

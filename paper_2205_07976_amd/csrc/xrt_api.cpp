@@ -762,6 +762,22 @@ xrt_status xrt_simulate_background(const xrt_detector *det, const xrt_beam *beam
     return XRT_OK;
 }
 
+xrt_status xrt_add_image(double *dev_acc, int32_t acc_nf, int32_t acc_ns, const void *dev_img, int32_t img_dtype,
+                         int32_t img_nf, int32_t img_ns, int32_t f0, int32_t s0, void *stream)
+{
+    if (!dev_acc || !dev_img) return fail(XRT_EINVAL, "NULL image");
+    if (img_dtype != XRT_F32 && img_dtype != XRT_F64) return fail(XRT_EINVAL, "unknown dtype %d", img_dtype);
+    if (acc_nf < 1 || acc_ns < 1 || img_nf < 1 || img_ns < 1) return fail(XRT_EINVAL, "image sizes must be >= 1");
+    if ((int64_t)acc_nf * acc_ns >= ((int64_t)1 << 40)) return fail(XRT_ERANGE, "accumulator has 2^40 or more pixels");
+    if (f0 < 0 || s0 < 0 || (int64_t)f0 + img_nf > acc_nf || (int64_t)s0 + img_ns > acc_ns)
+        return fail(XRT_EINVAL, "image [%d,%lld)x[%d,%lld) is outside the %dx%d accumulator", f0,
+                    (long long)f0 + img_nf, s0, (long long)s0 + img_ns, acc_nf, acc_ns);
+    const hipError_t e = xrt::launch_add_image(dev_acc, acc_nf, dev_img, img_dtype == XRT_F64, img_nf, img_ns, f0, s0,
+                                               (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "xrt_add_image");
+    return XRT_OK;
+}
+
 xrt_status xrt_trace_terms(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal,
                            int64_t n, const int32_t *host_idx, double *host_S, double *host_h)
 {

@@ -169,6 +169,8 @@ hipError_t launch_serve(const ServeArgs &a, int precision, int shape, int n_wg, 
 hipError_t launch_sinpi(const double *x, int64_t n, double *s64, float *s32, hipStream_t stream);
 hipError_t launch_exp(const double *x, int64_t n, double *y, hipStream_t stream);
 hipError_t launch_background(const BgParams &b, int precision, hipStream_t stream);
+hipError_t launch_add_image(double *acc, int64_t acc_nf, const void *img, int img_f64, int32_t nf, int32_t ns,
+                            int32_t f0, int32_t s0, hipStream_t stream);
 hipError_t launch_trace(const Params &p, int64_t n, const int32_t *idx, double *S, double *h,
                         hipStream_t stream);
 

@@ -1004,6 +1004,37 @@ hipError_t launch_background(const BgParams &b, int precision, hipStream_t strea
 }
 
 // ---------------------------------------------------------------------------
+// Ensemble sum (section III's add-image kernel, which adds the results of the
+// other kernels into one binary64 image): a region image of nf x ns pixels,
+// binary32 or binary64, added into a binary64 accumulator of acc_nf columns
+// at (f0, s0).  Memory-bound: per pixel one image read and one accumulator
+// read and write.  Rows are spread over blockIdx.y, columns over lanes, so
+// every wave reads and writes 64 consecutive pixels of one row.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void add_image_kernel(double *acc, int64_t acc_nf, const void *img, int img_f64,
+                                                          int nf, int ns, int f0, int s0)
+{
+    for (int r = blockIdx.y; r < ns; r += gridDim.y) {
+        double *row = acc + (int64_t)(s0 + r) * acc_nf + f0;
+        const int64_t base = (int64_t)r * nf;
+        for (int c = blockIdx.x * BLOCK + threadIdx.x; c < nf; c += gridDim.x * BLOCK) {
+            const double x = img_f64 ? ((const double *)img)[base + c] : (double)((const float *)img)[base + c];
+            row[c] = row[c] + x;
+        }
+    }
+}
+
+hipError_t launch_add_image(double *acc, int64_t acc_nf, const void *img, int img_f64, int32_t nf, int32_t ns,
+                            int32_t f0, int32_t s0, hipStream_t stream)
+{
+    const unsigned bx = (unsigned)std::min<int64_t>((nf + BLOCK - 1) / BLOCK, 64);
+    const unsigned by = (unsigned)std::min<int64_t>(ns, 8192);
+    hipLaunchKernelGGL(add_image_kernel, dim3(bx, by), dim3(BLOCK), 0, stream, acc, acc_nf, img, img_f64, nf, ns,
+                       f0, s0);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Padded F^2 tables: entry (a, b, c) of the (na+2P)(nb+2P)(nc+2P) box holds
 // F(a-P, b-P, c-P)^2 inside the tabulated range and F_default^2 elsewhere.
 // ---------------------------------------------------------------------------

@@ -104,7 +104,7 @@ SYMBOLS = ("xrt_version", "xrt_last_error", "xrt_fhkl_create", "xrt_fhkl_destroy
            "xrt_simulate", "xrt_simulate_rois", "xrt_backward_rois", "xrt_server_create",
            "xrt_server_destroy", "xrt_server_submit", "xrt_server_progress", "xrt_server_info",
            "xrt_server_image", "xrt_server_release", "xrt_server_cancel", "xrt_cell_mats", "xrt_trace_terms", "xrt_sinpi", "xrt_exp",
-           "xrt_simulate_background")
+           "xrt_simulate_background", "xrt_add_image")
 XRT_SHOT_QUEUED, XRT_SHOT_RUNNING, XRT_SHOT_DONE = 0, 1, 2
 
 
@@ -130,6 +130,8 @@ def load():
                                       C.c_int32, C.c_void_p, C.c_void_p]
     lib.xrt_simulate_background.argtypes = [C.POINTER(Detector), C.POINTER(Beam), C.POINTER(BackgroundDesc),
                                             C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
+    lib.xrt_add_image.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                  C.c_int32, C.c_int32, C.c_void_p]
     lib.xrt_server_create.argtypes = [C.POINTER(ServerDesc), C.c_void_p, C.POINTER(C.c_void_p)]
     lib.xrt_server_destroy.argtypes = [C.c_void_p]
     lib.xrt_server_submit.argtypes = [C.c_void_p, C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal),
@@ -281,6 +283,21 @@ def simulate_background(shot, bg, precision="fp64", out=None, out_dtype=None, ac
                                           C.c_void_p(out.data_ptr()), _dtype_code(out),
                                           int(bool(accumulate)), _stream(stream)))
     return out
+
+
+def add_image(acc, img, origin=(0, 0), stream=None):
+    """xrt_add_image: acc[s0:s0+ns, f0:f0+nf] += img in binary64, on the
+    stream (acc: a 2-D binary64 GPU tensor; img: 2-D binary32 or binary64 GPU
+    tensor; origin = (f0, s0)).  Returns acc."""
+    import torch
+    if not (acc.is_cuda and acc.dtype == torch.float64 and acc.dim() == 2 and acc.is_contiguous()):
+        raise ValueError("acc must be a contiguous 2-D binary64 GPU tensor")
+    if not (img.is_cuda and img.dim() == 2 and img.is_contiguous()):
+        raise ValueError("img must be a contiguous 2-D GPU tensor")
+    f0, s0 = (int(v) for v in origin)
+    _check(load().xrt_add_image(C.c_void_p(acc.data_ptr()), acc.shape[1], acc.shape[0], C.c_void_p(img.data_ptr()),
+                                _dtype_code(img), img.shape[1], img.shape[0], f0, s0, _stream(stream)))
+    return acc
 
 
 def _origins(origins):

@@ -153,6 +153,22 @@ def test_background_validation():
     assert _call_background(bad, x, F) == xrt.XRT_EINVAL
 
 
+def test_add_image_validation():
+    lib = xrt.load()
+    ok = dict(acc=8, anf=10, ans=10, img=8, dt=0, nf=4, ns=4, f0=0, s0=0)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.xrt_add_image(C.c_void_p(a["acc"]), a["anf"], a["ans"], C.c_void_p(a["img"]), a["dt"], a["nf"],
+                                 a["ns"], a["f0"], a["s0"], None)
+    for kw, code in [(dict(acc=0), xrt.XRT_EINVAL), (dict(img=0), xrt.XRT_EINVAL), (dict(dt=2), xrt.XRT_EINVAL),
+                     (dict(nf=0), xrt.XRT_EINVAL), (dict(anf=-1), xrt.XRT_EINVAL),
+                     (dict(f0=7), xrt.XRT_EINVAL), (dict(s0=-1), xrt.XRT_EINVAL), (dict(ns=11), xrt.XRT_EINVAL),
+                     (dict(anf=2 ** 30, ans=2 ** 10), xrt.XRT_ERANGE)]:
+        assert call(**kw) == code, kw
+        assert err()
+
+
 def test_fhkl_create_validation():
     lib = xrt.load()
     h = C.c_void_p()
