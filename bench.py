@@ -299,6 +299,50 @@ def serving_bench(n_cap=60, n_open=150, load=0.8):
             "closed_loop": closed, "poisson": opened, "load": load}
 
 
+def serving_io_bench(n_shots=40, write_ms=20.0, writers=4, budgets=(256 << 20, 64 << 20)):
+    """The served stream with every image written out by the client: each
+    image is written to a file and the writer then waits write_ms more (a
+    slow remote filesystem), under HBM budgets of 256 and 64 MiB.  A client that
+    copies each image from the device and writes it in its loop, against a
+    write-out server (images copied to pinned host memory on a copy stream,
+    device memory freed at once) with `writers` writer threads; and, between
+    the two, the in-place server with writer threads."""
+    import shutil
+    import tempfile
+    import numpy as np
+    import synth
+    from paper_2205_07976_amd import serve, xrt
+    base = synth.full_shot()
+    fh = xrt.Fhkl.from_shot(base)
+    rng = np.random.default_rng(31)
+    shots = [synth.served_shot(rng, base.F, base.hkl_min) for _ in range(n_shots)]
+    d = tempfile.mkdtemp(prefix="xrt_io_")
+    out = {"workload": f"{n_shots} served shots at once, mixed; every image written to a "
+                       f"file, then {write_ms:g} ms more per image"}
+
+    def sink(i, img):
+        path = os.path.join(d, f"img{i}.bin")
+        img.tofile(path)
+        os.remove(path)
+        time.sleep(write_ms * 1e-3)
+
+    try:
+        for budget in budgets:
+            for name, host_budget, nw in (("in_place_loop", 0, 0), ("in_place_threads", 0, writers),
+                                          ("write_out_threads", 2 << 30, writers)):
+                srv = xrt.Server(fh, hbm_budget=budget, max_resident=64, precision="mixed", host_budget=host_budget)
+                serve.run_stream(srv, shots[:2], np.zeros(2), sink=sink, writers=nw)
+                r = serve.summarize(serve.run_stream(srv, shots, np.zeros(n_shots), sink=sink, writers=nw), shots)
+                srv.close()
+                key = f"budget_{budget >> 20}MiB"
+                out.setdefault(key, {})[name] = r
+                log(f"serving with images written out, {key} {name}: {r['images_per_s']:.2f} img/s, "
+                    f"p50 {r['p50_ms']:.0f} ms")
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    return out
+
+
 def serving_sweep(n_cap=200, n_open=1000, loads=(0.5, 0.8, 0.95), small_budget=256 << 20):
     """The served stream at several offered loads: capacity from n_cap shots
     submitted at once, then n_open Poisson arrivals at each load x capacity;
@@ -430,6 +474,7 @@ def main():
         res["serving"] = serving_bench()
         res["p50_shot_latency_ms"] = res["serving"]["poisson"]["p50_ms"]
         res["p99_shot_latency_ms"] = res["serving"]["poisson"]["p99_ms"]
+        res["serving_io"] = serving_io_bench()
     if args.serve_sweep:
         res["serving_sweep"] = serving_sweep()
 

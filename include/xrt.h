@@ -296,6 +296,16 @@ xrt_status xrt_add_image(double *dev_acc, int32_t acc_nf, int32_t acc_ns, const 
  * Calls on one server are serialised internally; progress is driven by
  * xrt_server_progress (call it often: it admits, publishes, launches and
  * collects).  Limits per served shot: n_phi*n_mos <= 256, n_src <= 128.
+ *
+ * Write-out (host_budget > 0; the paper hides file I/O behind computation by
+ * running several producers per GPU, section IV): a shot that finishes on the
+ * device is copied into the server's pinned host memory on a copy stream
+ * while the persistent kernel goes on with other shots; when the copy is
+ * complete the shot's device memory and resident slot are freed and the shot
+ * is reported done, and its image is read with xrt_server_host_image.  Device
+ * memory thus never waits for a client that is still writing images out;
+ * host memory does (finished shots are copied in finishing order as host
+ * space frees up, each release making room).
  * --------------------------------------------------------------------------- */
 typedef struct xrt_server xrt_server;
 
@@ -312,6 +322,9 @@ typedef struct xrt_server_desc {
     double idle_exit_us;    /* once no workgroup has work and no chunk has
                                finished for this long, the kernel exits, in
                                [1, 1e6] us; the next progress call relaunches */
+    uint64_t host_budget;   /* pinned host bytes for written-out images: 0
+                               (images read in place from the device arena)
+                               or in [1 MiB, 1 TiB] */
 } xrt_server_desc;
 
 enum { XRT_SHOT_QUEUED = 0, XRT_SHOT_RUNNING = 1, XRT_SHOT_DONE = 2 };
@@ -338,7 +351,7 @@ xrt_status xrt_server_destroy(xrt_server *srv);
 
 /* Validate and queue one shot (the detector's ROI); copies every host array,
  * never blocks.  ERANGE if the shot exceeds the served limits or can never
- * fit the budget. */
+ * fit the budgets. */
 xrt_status xrt_server_submit(xrt_server *srv, const xrt_detector *det,
                              const xrt_beam *beam, const xrt_crystal *xtal,
                              uint64_t *ticket);
@@ -353,16 +366,25 @@ xrt_status xrt_server_progress(xrt_server *srv, int32_t *n_done);
 xrt_status xrt_server_info(xrt_server *srv, uint64_t ticket, xrt_shot_info *info);
 
 /* Device pointer of a finished shot's image inside the arena, valid until
- * xrt_server_release.  EBUSY if not done. */
+ * xrt_server_release.  EBUSY if not done; EINVAL on a server that writes
+ * images out. */
 xrt_status xrt_server_image(xrt_server *srv, uint64_t ticket, const void **dev_image);
 
-/* Free a finished shot's memory and slot.  EBUSY if not done. */
+/* Write-out servers: pointer to a finished shot's image in the server's
+ * pinned host memory ([roi_ns][roi_nf] of out_dtype), valid until
+ * xrt_server_release.  EBUSY if not done (the copy may still run); EINVAL on
+ * a server without a host budget. */
+xrt_status xrt_server_host_image(xrt_server *srv, uint64_t ticket, const void **host_image);
+
+/* Free a finished shot's memory and slot (write-out: its host memory; the
+ * device memory and the slot were freed when the copy completed).  EBUSY if
+ * not done. */
 xrt_status xrt_server_release(xrt_server *srv, uint64_t ticket);
 
 /* Withdraw a shot that is still queued (not yet admitted): the ticket is
  * forgotten and the shots behind it move up.  EBUSY once the shot has been
- * admitted (its work may be on the device: wait for it and release it);
- * EINVAL for an unknown ticket. */
+ * admitted (its work may be on the device: wait for it and release it) or is
+ * done; EINVAL for an unknown ticket. */
 xrt_status xrt_server_cancel(xrt_server *srv, uint64_t ticket);
 
 /* Diagnostics: the kernels' sin(pi x) for |x| <= 1/2 (the reduced arguments f

@@ -17,6 +17,12 @@
 //                 published chunks wait.
 //   image / release   read a finished image in place, then free its memory.
 //
+// With write-out (a host budget), a shot that finishes on the device is
+// copied into pinned host memory on a copy stream while the persistent kernel
+// goes on with other shots; once the copy is complete the shot's device memory
+// and resident slot are freed and the shot is reported done, so admission
+// never waits for a client that is still writing earlier images out.
+//
 // Work of shots admitted while others run joins the same persistent kernel
 // (continuous batching); every pixel is computed by the same arithmetic as
 // xrt_simulate, so a shot's image does not depend on the mix it ran in.
@@ -66,6 +72,11 @@ struct Shot {
     std::vector<double> dir, lam, weight, umats;
     uint64_t image_bytes = 0, part_bytes = 0;
     double t_submit = 0, t_admit = -1, t_done = -1;
+    // write-out: the image's place in the host arena and the copy's event;
+    // written once the copy has completed (the device memory is gone then)
+    uint64_t out_off = 0;
+    hipEvent_t copied = nullptr;
+    bool written = false;
 };
 
 }  // namespace
@@ -87,6 +98,15 @@ struct xrt_server {
     uint32_t *done = nullptr;
     hipStream_t work = nullptr;              // the persistent kernel's stream
     hipEvent_t kernel_done = nullptr;
+    // write-out (desc.host_budget > 0): pinned host arena of finished images,
+    // the copy stream, shots finished on the device that wait for host space
+    // (in finishing order), copies in flight, and spare events
+    char *out = nullptr;
+    xrt::sched::Arena *out_arena = nullptr;
+    hipStream_t copy = nullptr;
+    std::deque<uint64_t> to_copy;
+    std::vector<uint64_t> copying;
+    std::vector<hipEvent_t> spare_events;
     bool launched = false;
     int n_wg = 0;
     uint64_t next_ticket = 1;
@@ -112,11 +132,20 @@ xrt_status check_desc(const xrt_server_desc *d)
     if (d->out_dtype != XRT_F32 && d->out_dtype != XRT_F64) return fail(XRT_EINVAL, "unknown out_dtype");
     if (d->workgroups < 0 || d->workgroups > 65536) return fail(XRT_ERANGE, "workgroups must be in [0, 65536]");
     if (!(d->idle_exit_us >= 1.0 && d->idle_exit_us <= 1e6)) return fail(XRT_ERANGE, "idle_exit_us must be in [1, 1e6]");
+    if (d->host_budget != 0 && (d->host_budget < (1u << 20) || d->host_budget > ((uint64_t)1 << 40)))
+        return fail(XRT_ERANGE, "host_budget must be 0 or in [1 MiB, 1 TiB]");
     return XRT_OK;
 }
 
 void free_server(xrt_server *s)
 {
+    if (s->copy) (void)hipStreamSynchronize(s->copy);
+    for (auto &kv : s->shots)
+        if (kv.second.copied) (void)hipEventDestroy(kv.second.copied);
+    for (hipEvent_t e : s->spare_events) (void)hipEventDestroy(e);
+    if (s->copy) (void)hipStreamDestroy(s->copy);
+    if (s->out) (void)hipHostFree(s->out);
+    delete s->out_arena;
     if (s->kernel_done) (void)hipEventDestroy(s->kernel_done);
     if (s->work) (void)hipStreamDestroy(s->work);
     if (s->dev_arena) (void)hipFree(s->dev_arena);
@@ -142,14 +171,88 @@ bool kernel_running(xrt_server *s, hipError_t *err)
     return false;
 }
 
-// (1) done flags -> finished chunks -> finished phases and shots.
-void collect(xrt_server *s, int32_t *n_done)
+// Write-out: copies of finished shots into the host arena, in finishing
+// order, as far as host space allows (the first that does not fit waits for
+// releases, and the ones behind it wait too).
+xrt_status start_copies(xrt_server *s)
+{
+    while (!s->to_copy.empty()) {
+        const uint64_t t = s->to_copy.front();
+        Shot &sh = s->shots[t];
+        const xrt::sched::Work *w = s->sched->find(t);
+        uint64_t off = 0;
+        if (!s->out_arena->alloc(align_up(sh.image_bytes), &off)) break;
+        hipEvent_t ev = nullptr;
+        hipError_t e = hipSuccess;
+        if (!s->spare_events.empty()) {
+            ev = s->spare_events.back();
+            s->spare_events.pop_back();
+        } else {
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        }
+        // the kernel wrote the image and made it visible at system scope
+        // before raising the done flags that finished this shot
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->out + off, s->dev_arena + w->dev_off, sh.image_bytes, hipMemcpyDeviceToHost, s->copy);
+        if (e == hipSuccess) e = hipEventRecord(ev, s->copy);
+        if (e != hipSuccess) {
+            s->out_arena->release(off, align_up(sh.image_bytes));
+            if (ev) s->spare_events.push_back(ev);
+            return hip_fail(e, "xrt_server_progress: image copy");
+        }
+        sh.out_off = off;
+        sh.copied = ev;
+        s->copying.push_back(t);
+        s->to_copy.pop_front();
+    }
+    return XRT_OK;
+}
+
+// Write-out: completed copies free the shot's device memory and slot and make
+// it done.  Returns the number of shots finished so.
+xrt_status finish_copies(xrt_server *s, int32_t *n)
+{
+    size_t k = 0;
+    for (size_t i = 0; i < s->copying.size(); ++i) {
+        const uint64_t t = s->copying[i];
+        Shot &sh = s->shots[t];
+        const hipError_t e = hipEventQuery(sh.copied);
+        if (e == hipErrorNotReady) {
+            s->copying[k++] = t;
+            continue;
+        }
+        if (e != hipSuccess) return hip_fail(e, "xrt_server_progress: image copy");
+        s->spare_events.push_back(sh.copied);
+        sh.copied = nullptr;
+        sh.written = true;
+        sh.t_done = s->now();
+        s->sched->release(t);
+        ++*n;
+    }
+    s->copying.resize(k);
+    return XRT_OK;
+}
+
+// (1) done flags -> finished chunks -> finished phases and shots; with
+// write-out, finished shots go to the copy queue and completed copies finish
+// them.
+xrt_status collect(xrt_server *s, int32_t *n_done)
 {
     std::vector<uint64_t> finished;
     s->sched->collect([s](uint64_t seq) { return __atomic_load_n(&s->done[seq % RING], __ATOMIC_ACQUIRE) == (uint32_t)(seq + 1); },
                       &finished);
-    for (uint64_t t : finished) s->shots[t].t_done = s->now();
-    if (n_done) *n_done = (int32_t)finished.size();
+    int32_t n = 0;
+    if (!s->out) {
+        for (uint64_t t : finished) s->shots[t].t_done = s->now();
+        n = (int32_t)finished.size();
+    } else {
+        for (uint64_t t : finished) s->to_copy.push_back(t);
+        xrt_status st = finish_copies(s, &n);
+        if (!st) st = start_copies(s);
+        if (st) return st;
+    }
+    if (n_done) *n_done = n;
+    return XRT_OK;
 }
 
 // (2) admission (in arrival order, by device-arena footprint and resident
@@ -263,6 +366,10 @@ xrt_status xrt_server_create(const xrt_server_desc *desc, const xrt_fhkl *fhkl, 
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->done, sizeof(uint32_t) * RING, hipHostMallocCoherent);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->host_arena, s->host_bytes, hipHostMallocCoherent);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->work, hipStreamNonBlocking);
+    if (e == hipSuccess && desc->host_budget) {
+        e = hipHostMalloc((void **)&s->out, desc->host_budget, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
+    }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->kernel_done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -273,7 +380,8 @@ xrt_status xrt_server_create(const xrt_server_desc *desc, const xrt_fhkl *fhkl, 
     std::memset(s->ring, 0, sizeof(xrt::ServeChunk) * RING);
     std::memset(s->done, 0, sizeof(uint32_t) * RING);
     s->sched = new (std::nothrow) xrt::sched::Scheduler(desc->hbm_budget, s->host_bytes, desc->max_resident, s->n_wg, RING);
-    if (!s->sched) {
+    if (s->out) s->out_arena = new (std::nothrow) xrt::sched::Arena(desc->host_budget);
+    if (!s->sched || (s->out && !s->out_arena)) {
         free_server(s);
         return fail(XRT_ENOMEM, "host allocation failed");
     }
@@ -329,6 +437,9 @@ xrt_status xrt_server_submit(xrt_server *s, const xrt_detector *det, const xrt_b
     if (w.footprint > s->desc.hbm_budget)
         return fail(XRT_ERANGE, "shot needs %llu bytes, more than the server's budget %llu",
                     (unsigned long long)w.footprint, (unsigned long long)s->desc.hbm_budget);
+    if (s->desc.host_budget && align_up(sh.image_bytes) > s->desc.host_budget)
+        return fail(XRT_ERANGE, "image of %llu bytes exceeds the server's host budget %llu",
+                    (unsigned long long)sh.image_bytes, (unsigned long long)s->desc.host_budget);
     std::lock_guard<std::mutex> g(s->mu);
     w.ticket = s->next_ticket++;
     sh.t_submit = s->now();
@@ -347,8 +458,9 @@ xrt_status xrt_server_progress(xrt_server *s, int32_t *n_done)
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     if (dev != s->device) return fail(XRT_EINVAL, "server lives on device %d, current device is %d", s->device, dev);
-    collect(s, n_done);
-    xrt_status st = admit(s);
+    xrt_status st = collect(s, n_done);
+    if (st) return st;
+    st = admit(s);
     if (st) return st;
     publish(s);
     // a kernel that ended (idle exit) is relaunched when published work waits
@@ -366,7 +478,9 @@ xrt_status xrt_server_info(xrt_server *s, uint64_t ticket, xrt_shot_info *info)
     if (it == s->shots.end()) return fail(XRT_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
     const Shot &sh = it->second;
     const xrt::sched::Work *w = s->sched->find(ticket);
-    info->state = w ? w->state : XRT_SHOT_DONE;
+    // with write-out a shot is done once its image is on the host (the
+    // scheduler has forgotten it by then); until then it is running
+    info->state = w ? (s->out && w->state == xrt::sched::DONE ? XRT_SHOT_RUNNING : w->state) : XRT_SHOT_DONE;
     info->image_bytes = sh.image_bytes;
     info->roi_nf = sh.det.roi_f1 - sh.det.roi_f0;
     info->roi_ns = sh.det.roi_s1 - sh.det.roi_s0;
@@ -380,10 +494,23 @@ xrt_status xrt_server_image(xrt_server *s, uint64_t ticket, const void **dev_ima
 {
     if (!s || !dev_image) return fail(XRT_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> g(s->mu);
+    if (s->out) return fail(XRT_EINVAL, "this server writes images out: use xrt_server_host_image");
     const xrt::sched::Work *w = s->sched->find(ticket);
     if (!w) return fail(XRT_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
     if (w->state != xrt::sched::DONE) return fail(XRT_EBUSY, "shot %llu is not done", (unsigned long long)ticket);
     *dev_image = s->dev_arena + w->dev_off;
+    return XRT_OK;
+}
+
+xrt_status xrt_server_host_image(xrt_server *s, uint64_t ticket, const void **host_image)
+{
+    if (!s || !host_image) return fail(XRT_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(s->mu);
+    if (!s->out) return fail(XRT_EINVAL, "this server has no host budget: use xrt_server_image");
+    auto it = s->shots.find(ticket);
+    if (it == s->shots.end()) return fail(XRT_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    if (!it->second.written) return fail(XRT_EBUSY, "shot %llu is not done", (unsigned long long)ticket);
+    *host_image = s->out + it->second.out_off;
     return XRT_OK;
 }
 
@@ -392,6 +519,8 @@ xrt_status xrt_server_cancel(xrt_server *s, uint64_t ticket)
     if (!s) return fail(XRT_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> g(s->mu);
     const xrt::sched::Work *w = s->sched->find(ticket);
+    if (!w && s->shots.count(ticket))  // written out: done
+        return fail(XRT_EBUSY, "shot %llu is already done", (unsigned long long)ticket);
     if (!w) return fail(XRT_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
     if (w->state != xrt::sched::QUEUED)
         return fail(XRT_EBUSY, "shot %llu is already admitted", (unsigned long long)ticket);
@@ -404,6 +533,14 @@ xrt_status xrt_server_release(xrt_server *s, uint64_t ticket)
 {
     if (!s) return fail(XRT_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> g(s->mu);
+    if (s->out) {
+        auto it = s->shots.find(ticket);
+        if (it == s->shots.end()) return fail(XRT_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+        if (!it->second.written) return fail(XRT_EBUSY, "shot %llu is not done", (unsigned long long)ticket);
+        s->out_arena->release(it->second.out_off, align_up(it->second.image_bytes));
+        s->shots.erase(it);
+        return XRT_OK;
+    }
     const xrt::sched::Work *w = s->sched->find(ticket);
     if (!w) return fail(XRT_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
     if (w->state != xrt::sched::DONE) return fail(XRT_EBUSY, "shot %llu is not done", (unsigned long long)ticket);

@@ -18,12 +18,17 @@ def poisson_arrivals(rng: np.random.Generator, n: int, rate: float) -> np.ndarra
     return np.cumsum(rng.exponential(1.0 / rate, n))
 
 
-def run_stream(server, shots, arrivals, keep=None, on_done=None, timeout=600.0):
+def run_stream(server, shots, arrivals, keep=None, on_done=None, timeout=600.0, sink=None, writers=0):
     """Serve ``shots`` arriving at ``arrivals`` (seconds, nondecreasing).
 
-    keep:     indices whose images are copied out before release (returned).
+    keep:     indices whose images are copied out before release (returned:
+              device tensors, or host arrays from a write-out server).
     on_done:  callback(index, ticket) run when a shot finishes, before release.
-    Returns a dict with per-shot latency, admission wait and the makespan."""
+    sink:     callback(index, host image) for every shot (writing it out, say),
+              then the release; run in the loop, or by ``writers`` threads
+              while the loop keeps driving the server.
+    Returns a dict with per-shot latency, admission wait and the makespan
+    (which includes the sinks)."""
     keep = set(keep or ())
     n = len(shots)
     tickets = [None] * n
@@ -33,6 +38,16 @@ def run_stream(server, shots, arrivals, keep=None, on_done=None, timeout=600.0):
     pending = {}
     nxt = 0
     done = 0
+    pool = None
+    jobs = []
+    if sink is not None and writers > 0:
+        from concurrent.futures import ThreadPoolExecutor
+        pool = ThreadPoolExecutor(max_workers=writers)
+
+    def finish(i, t):
+        sink(i, fetch(server, t))
+        server.release(t)
+
     t0 = time.perf_counter()
     while done < n:
         now = time.perf_counter() - t0
@@ -52,18 +67,35 @@ def run_stream(server, shots, arrivals, keep=None, on_done=None, timeout=600.0):
             latency[i] = info.t_done - info.t_submit
             wait[i] = info.t_admit - info.t_submit
             if i in keep:
-                images[i] = server.image(t)
+                images[i] = server.host_image(t) if getattr(server, "writes_out", False) else server.image(t)
             if on_done is not None:
                 on_done(i, t)
-            server.release(t)
+            if sink is None:
+                server.release(t)
+            elif pool is None:
+                finish(i, t)
+            else:
+                jobs.append(pool.submit(finish, i, t))
             del pending[t]
             done += 1
         if not finished and nxt < n and not pending:
             # idle until the next arrival
             time.sleep(max(0.0, min(arrivals[nxt] - (time.perf_counter() - t0), 0.001)))
+    if pool is not None:
+        for j in jobs:
+            j.result()
+        pool.shutdown()
     makespan = time.perf_counter() - t0
     return {"latency": latency, "admission_wait": wait, "makespan": makespan, "images": images,
             "tickets": tickets}
+
+
+def fetch(server, ticket) -> np.ndarray:
+    """A finished image on the host: read from the server's pinned host
+    memory (write-out servers) or copied from the device arena."""
+    if getattr(server, "writes_out", False):
+        return server.host_image(ticket)
+    return server.image(ticket, copy=False).cpu().numpy()
 
 
 def summarize(result, shots, offered_rate=None):

@@ -79,7 +79,7 @@ class ServerDesc(C.Structure):
     _fields_ = [
         ("struct_size", C.c_uint32), ("hbm_budget", C.c_uint64), ("max_resident", C.c_int32),
         ("precision", C.c_int32), ("shape", C.c_int32), ("out_dtype", C.c_int32),
-        ("workgroups", C.c_int32), ("idle_exit_us", C.c_double),
+        ("workgroups", C.c_int32), ("idle_exit_us", C.c_double), ("host_budget", C.c_uint64),
     ]
 
 
@@ -103,7 +103,7 @@ _lib = None
 SYMBOLS = ("xrt_version", "xrt_last_error", "xrt_fhkl_create", "xrt_fhkl_destroy",
            "xrt_simulate", "xrt_simulate_rois", "xrt_backward_rois", "xrt_server_create",
            "xrt_server_destroy", "xrt_server_submit", "xrt_server_progress", "xrt_server_info",
-           "xrt_server_image", "xrt_server_release", "xrt_server_cancel", "xrt_cell_mats", "xrt_trace_terms", "xrt_sinpi", "xrt_exp",
+           "xrt_server_image", "xrt_server_host_image", "xrt_server_release", "xrt_server_cancel", "xrt_cell_mats", "xrt_trace_terms", "xrt_sinpi", "xrt_exp",
            "xrt_simulate_background", "xrt_add_image")
 XRT_SHOT_QUEUED, XRT_SHOT_RUNNING, XRT_SHOT_DONE = 0, 1, 2
 
@@ -139,6 +139,7 @@ def load():
     lib.xrt_server_progress.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
     lib.xrt_server_info.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(ShotInfo)]
     lib.xrt_server_image.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_void_p)]
+    lib.xrt_server_host_image.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_void_p)]
     lib.xrt_server_release.argtypes = [C.c_void_p, C.c_uint64]
     lib.xrt_server_cancel.argtypes = [C.c_void_p, C.c_uint64]
     lib.xrt_cell_mats.argtypes = [C.POINTER(Crystal), C.c_void_p]
@@ -401,11 +402,12 @@ class Server:
     a torch tensor viewing the server's arena (copy it before release)."""
 
     def __init__(self, fhkl: Fhkl, hbm_budget=8 << 30, max_resident=256, precision="mixed",
-                 shape=XRT_SHAPE_SINCG, out_dtype=None, workgroups=0, idle_exit_us=5000.0):
+                 shape=XRT_SHAPE_SINCG, out_dtype=None, workgroups=0, idle_exit_us=5000.0, host_budget=0):
         self.fhkl = fhkl  # kept alive: the server borrows its tables
         self.out_f64 = (out_dtype == "f64") if out_dtype else precision == "fp64"
+        self.writes_out = bool(host_budget)
         d = ServerDesc(C.sizeof(ServerDesc), int(hbm_budget), int(max_resident), _PREC[precision], int(shape),
-                       XRT_F64 if self.out_f64 else XRT_F32, int(workgroups), float(idle_exit_us))
+                       XRT_F64 if self.out_f64 else XRT_F32, int(workgroups), float(idle_exit_us), int(host_budget))
         h = C.c_void_p()
         _check(load().xrt_server_create(C.byref(d), fhkl.handle, C.byref(h)))
         self._h = h
@@ -443,6 +445,16 @@ class Server:
 
         view = torch.as_tensor(_View(), device="cuda")
         return view.clone() if copy else view
+
+    def host_image(self, ticket):
+        """Write-out servers: the finished image in the server's pinned host
+        memory, copied into a numpy array [roi_ns, roi_nf]."""
+        info = self.info(ticket)
+        p = C.c_void_p()
+        _check(load().xrt_server_host_image(self._h, int(ticket), C.byref(p)))
+        ct = C.c_double if self.out_f64 else C.c_float
+        buf = (ct * (info.roi_ns * info.roi_nf)).from_address(p.value)
+        return np.ctypeslib.as_array(buf).reshape(info.roi_ns, info.roi_nf).copy()
 
     def release(self, ticket):
         _check(load().xrt_server_release(self._h, int(ticket)))

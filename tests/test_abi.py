@@ -225,3 +225,17 @@ def test_server_calls_reject_null():
     assert lib.xrt_server_release(None, 1) == xrt.XRT_EINVAL
     assert lib.xrt_server_progress(None, None) == xrt.XRT_EINVAL
     assert lib.xrt_server_destroy(None) == xrt.XRT_OK
+    p = C.c_void_p()
+    assert lib.xrt_server_host_image(None, 1, C.byref(p)) == xrt.XRT_EINVAL
+
+
+def test_server_desc_host_budget_range():
+    """The host budget of write-out servers is validated before any device
+    work: 0 (off) or [1 MiB, 1 TiB]."""
+    lib = xrt.load()
+    h = C.c_void_p()
+    for budget in (1, (1 << 20) - 1, (1 << 40) + 1):
+        d = xrt.ServerDesc(C.sizeof(xrt.ServerDesc), 1 << 30, 8, xrt.XRT_MIXED, xrt.XRT_SHAPE_SINCG, xrt.XRT_F32,
+                           0, 5000.0, budget)
+        assert lib.xrt_server_create(C.byref(d), C.c_void_p(8), C.byref(h)) == xrt.XRT_ERANGE
+        assert "host_budget" in err()

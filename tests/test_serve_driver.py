@@ -76,6 +76,37 @@ def test_run_stream_with_fake_server():
     assert not srv.shots  # everything released
 
 
+class FakeWriteOutServer(FakeServer):
+    """The fake server with write-out: images are host arrays."""
+    writes_out = True
+
+    def host_image(self, t):
+        assert self.shots[t]["done"] >= 0
+        return np.full((2, 3), float(t))
+
+
+@pytest.mark.parametrize("writers", [0, 3])
+def test_run_stream_sinks_every_image_then_releases(writers):
+    """Every finished shot's host image reaches the sink exactly once, before
+    its release, in the loop or on writer threads."""
+    import threading
+    shots = [synth.tiny_shot()] * 15
+    srv = FakeWriteOutServer(slots=3, service=0.002)
+    seen, lock = {}, threading.Lock()
+
+    def sink(i, img):
+        time.sleep(0.003)  # a slow writer
+        with lock:
+            assert i not in seen
+            seen[i] = img
+
+    res = serve.run_stream(srv, shots, np.zeros(len(shots)), sink=sink, writers=writers)
+    assert sorted(seen) == list(range(15))
+    for i, img in seen.items():
+        assert np.all(img == res["tickets"][i])
+    assert not srv.shots
+
+
 def test_poisson_arrivals_rate():
     a = serve.poisson_arrivals(np.random.default_rng(2), 20000, rate=50.0)
     assert np.all(np.diff(a) > 0)
