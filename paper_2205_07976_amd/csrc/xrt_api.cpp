@@ -708,9 +708,10 @@ xrt_status xrt_simulate_background(const xrt_detector *det, const xrt_beam *beam
     const int32_t nf = det->roi_f1 - det->roi_f0, ns = det->roi_s1 - det->roi_s0;
     const int n = bg->n_knots, n_src = beam->n_src;
 
-    // one upload: [sources | origin | knots | sources (binary32) | knots (binary32)]
+    // one upload: [sources | origin | knots | sources (binary32, with the low
+    // parts of the directions) | knots (binary32)]
     const size_t o_orig = xrt::SRC_STRIDE * (size_t)n_src, o_k64 = o_orig + 1, o_s32 = o_k64 + 3 * (size_t)n;
-    const size_t o_k32 = o_s32 + (xrt::SRC_STRIDE * (size_t)n_src + 1) / 2;
+    const size_t o_k32 = o_s32 + xrt::SRC32_STRIDE * (size_t)n_src / 2;
     std::vector<double> host(o_k32 + (3 * (size_t)n + 1) / 2, 0.0);
     build_sources(beam, host.data());
     const int32_t origin[2] = {det->roi_f0, det->roi_s0};
@@ -724,7 +725,13 @@ xrt_status xrt_simulate_background(const xrt_detector *det, const xrt_beam *beam
         k64[3 * k + 2] = k + 1 < n ? (bg->F[k + 1] - bg->F[k]) / (bg->stol[k + 1] - bg->stol[k]) : 0.0;
         for (int c = 0; c < 3; ++c) k32[3 * k + c] = (float)k64[3 * k + c];
     }
-    for (size_t i = 0; i < xrt::SRC_STRIDE * (size_t)n_src; ++i) s32[i] = (float)host[i];
+    for (int j = 0; j < n_src; ++j) {
+        const double *row = host.data() + xrt::SRC_STRIDE * (size_t)j;
+        float *r32 = s32 + xrt::SRC32_STRIDE * (size_t)j;
+        for (int i = 0; i < xrt::SRC_STRIDE; ++i) r32[i] = (float)row[i];
+        for (int i = 0; i < 3; ++i)  // dir = r32[i] + r32[LO + i] to about 2^-48
+            r32[xrt::SRC32_DIR_LO + i] = (float)(row[xrt::SRC_DIR + i] - (double)r32[xrt::SRC_DIR + i]);
+    }
 
     xrt::BgParams b;
     std::memset(&b, 0, sizeof b);

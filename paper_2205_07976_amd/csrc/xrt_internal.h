@@ -144,11 +144,14 @@ struct ServeArgs {
 // r_e^2 fluence molecules / O^2) and the scattering curve as knots
 // (stol_k, F_k, slope_k) with slope_{n-1} = 0, in binary64 and binary32.
 constexpr int BG_MAX_KNOTS = 1024;
+constexpr int SRC32_STRIDE = 16;
+constexpr int SRC32_DIR_LO = 12;
 struct BgParams {
     Params p;
     const double *knots64;  // [n_knots][3]
     const float *knots32;   // [n_knots][3]
-    const float *src32;     // [n_src][SRC_STRIDE] binary32 copies of the source rows
+    const float *src32;     // [n_src][SRC32_STRIDE]: binary32 copies of the source
+                            // rows, then dir - (double)(float)dir at SRC32_DIR_LO
     int32_t n_knots;
     int32_t pad;
 };

@@ -970,16 +970,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
                     }
                     acc64 = __builtin_fma(wgeo, sub, acc64);
                 } else {
-                    // d - dir in binary64 (it cancels near the direct beam),
-                    // everything after it in binary32
+                    // d - dir cancels near the direct beam: d and dir are
+                    // each split into a binary32 head and the binary32 rest,
+                    // the heads subtract exactly there (Sterbenz), and the
+                    // rests add back what binary64 would have kept
                     const float d32[3] = {(float)d[0], (float)d[1], (float)d[2]};
+                    const float dlo[3] = {(float)(d[0] - (double)d32[0]), (float)(d[1] - (double)d32[1]),
+                                          (float)(d[2] - (double)d32[2])};
                     float s = 0.0f, c = 0.0f;
 #pragma unroll 2
                     for (int j = 0; j < p.n_src; ++j) {
-                        const double *src = p.src + SRC_STRIDE * j;
-                        const float *src32 = b.src32 + SRC_STRIDE * j;
-                        const float e0 = (float)(d[0] - src[SRC_DIR]), e1 = (float)(d[1] - src[SRC_DIR + 1]),
-                                    e2 = (float)(d[2] - src[SRC_DIR + 2]);
+                        const float *src32 = b.src32 + SRC32_STRIDE * j;
+                        const float e0 = (d32[0] - src32[SRC_DIR]) + (dlo[0] - src32[SRC32_DIR_LO]);
+                        const float e1 = (d32[1] - src32[SRC_DIR + 1]) + (dlo[1] - src32[SRC32_DIR_LO + 1]);
+                        const float e2 = (d32[2] - src32[SRC_DIR + 2]) + (dlo[2] - src32[SRC32_DIR_LO + 2]);
                         const float len = root_small(__builtin_fmaf(e2, e2, __builtin_fmaf(e1, e1, e0 * e0)));
                         const float F = bg_curve(kt, k, len * src32[SRC_HIL]);
                         const float P = bg_polarization(src32, d32, (float)p.kahn);
