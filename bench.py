@@ -41,11 +41,11 @@ C_ALG = {"fp64": 204, "mixed": 129}
 #             interval test 2 compares, interpolation 2, F^2 1, Kahn factor
 #             (3 dot products 9 + 5), w P 1, accumulate 1
 #             -> 6 + 6 + 18 + 2 + 2 + 4 + 4 + 2 + 28 + 4 = 76
-#   mixed:    d - dir 3 binary64 subs and 3 conversions (12); then binary32:
-#             square 3, root 4, scale 1, clamp 1, compares 2, interpolation 2,
-#             F^2 1, Kahn factor 14, products 2, Kahan add 4
-#             -> 12 + 3 + 4 + 1 + 1 + 2 + 2 + 1 + 14 + 2 + 4 = 46
-C_ALG_BG = {"fp64": 76, "mixed": 46}
+#   mixed:    binary32 throughout: d - dir from heads and tails 9, square 3,
+#             root 4, scale 1, clamp 1, compares 2, interpolation 2, F^2 1,
+#             Kahn factor 14, products 2, Kahan add 4
+#             -> 9 + 3 + 4 + 1 + 1 + 2 + 2 + 1 + 14 + 2 + 4 = 43
+C_ALG_BG = {"fp64": 76, "mixed": 43}
 # The refinement step (Gaussian shape), per pixel term, same units:
 #   forward binary64: h 12 ops, per axis rint, sub, square, FMA (12 ops), exp
 #             (clamp, scale, rint, 2 reduction FMAs, 11 Horner FMAs, ldexp,
