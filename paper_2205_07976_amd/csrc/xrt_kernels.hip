@@ -1028,9 +1028,49 @@ __global__ __launch_bounds__(BLOCK) void add_image_kernel(double *acc, int64_t a
     }
 }
 
+// The same when the image covers whole accumulator rows (a contiguous run of
+// n pixels) and both starts are 16-byte aligned: four pixels per lane and
+// step, as one 16-byte image load (binary32; two for binary64) and two
+// 16-byte accumulator loads and stores; the n mod 4 last pixels one by one.
+__global__ __launch_bounds__(BLOCK) void add_image_flat_kernel(double *acc, const void *img, int img_f64, int64_t n)
+{
+    const int64_t n4 = n >> 2, stride = (int64_t)gridDim.x * BLOCK;
+    double2 *a2 = reinterpret_cast<double2 *>(acc);
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n4; i += stride) {
+        double2 x0, x1;
+        if (img_f64) {
+            const double2 *g = reinterpret_cast<const double2 *>(img);
+            x0 = g[2 * i];
+            x1 = g[2 * i + 1];
+        } else {
+            const float4 f = reinterpret_cast<const float4 *>(img)[i];
+            x0 = make_double2(f.x, f.y);
+            x1 = make_double2(f.z, f.w);
+        }
+        double2 a0 = a2[2 * i], a1 = a2[2 * i + 1];
+        a0.x = a0.x + x0.x;
+        a0.y = a0.y + x0.y;
+        a1.x = a1.x + x1.x;
+        a1.y = a1.y + x1.y;
+        a2[2 * i] = a0;
+        a2[2 * i + 1] = a1;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
+        const int64_t j = (n4 << 2) + threadIdx.x;
+        acc[j] = acc[j] + (img_f64 ? ((const double *)img)[j] : (double)((const float *)img)[j]);
+    }
+}
+
 hipError_t launch_add_image(double *acc, int64_t acc_nf, const void *img, int img_f64, int32_t nf, int32_t ns,
                             int32_t f0, int32_t s0, hipStream_t stream)
 {
+    double *start = acc + (int64_t)s0 * acc_nf + f0;
+    if (f0 == 0 && nf == acc_nf && ((uintptr_t)start & 15) == 0 && ((uintptr_t)img & 15) == 0) {
+        const int64_t n = (int64_t)nf * ns;
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(((n >> 2) + BLOCK - 1) / BLOCK, 8192));
+        hipLaunchKernelGGL(add_image_flat_kernel, dim3(grid), dim3(BLOCK), 0, stream, start, img, img_f64, n);
+        return hipGetLastError();
+    }
     const unsigned bx = (unsigned)std::min<int64_t>((nf + BLOCK - 1) / BLOCK, 64);
     const unsigned by = (unsigned)std::min<int64_t>(ns, 8192);
     hipLaunchKernelGGL(add_image_kernel, dim3(bx, by), dim3(BLOCK), 0, stream, acc, acc_nf, img, img_f64, nf, ns,

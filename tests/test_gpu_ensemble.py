@@ -27,11 +27,15 @@ def say(*a):
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_add_image_matches_definition(dtype):
     """Random placements, ragged sizes, a single pixel, the whole
-    accumulator, the four edges: bit for bit."""
+    accumulator, whole rows, the four edges: bit for bit."""
     rng = np.random.default_rng(3)
     acc0 = rng.standard_normal((300, 517))
+    # whole rows at 16-byte aligned starts take the four-pixels-per-lane path
+    # (1-pixel tails at 517 x 37 and 517 x 1); 517 x 3 at row 11 starts 8
+    # bytes off and takes the row path like the rest
     cases = [((1, 1), (0, 0)), ((517, 300), (0, 0)), ((19, 7), (498, 293)), ((300, 1), (217, 0)),
-             ((1, 300), (0, 0)), ((257, 129), (100, 50)), ((64, 64), (453, 236))]
+             ((1, 300), (0, 0)), ((257, 129), (100, 50)), ((64, 64), (453, 236)), ((517, 37), (0, 16)),
+             ((517, 1), (0, 8)), ((517, 3), (0, 11))]
     acc = torch.as_tensor(acc0, device="cuda")
     ref = acc0
     for (nf, ns), (f0, s0) in cases:
