@@ -897,20 +897,22 @@ template <typename R>
 struct alignas(4 * sizeof(R)) BgKnot {
     R x, xn, y, m;
 };
-// The curve at s, with k the lane's interval from its previous term: walk
-// down while the knot is above s, then up while the next knot is at or below
-// s.  Successive terms of a pixel (sources of nearby wavelength, neighbouring
-// sub-pixels) nearly always stay in the same interval, so a lookup is one LDS
-// read of a record and two compares.  s is clamped to the first knot, so the
-// downward walk stops at 0; the NaN after the last knot compares false, so
-// the upward walk stops at n - 1.
+// The curve at s.  The lane keeps the record c of its previous term's
+// interval k in registers; successive terms of a pixel (sources of nearby
+// wavelength, neighbouring sub-pixels) nearly always stay in it, so a lookup
+// is two compares and no LDS read.  Otherwise it walks through the LDS
+// records: down while the knot is above s, then up while the next knot is at
+// or below s.  s is clamped to the first knot x0, so the downward walk stops
+// at 0; the NaN after the last knot compares false, so the upward walk stops
+// at n - 1.
 template <typename R>
-__device__ __forceinline__ R bg_curve(const BgKnot<R> *kt, int &k, R s)
+__device__ __forceinline__ R bg_curve(const BgKnot<R> *kt, BgKnot<R> &c, int &k, R x0, R s)
 {
-    s = max_r(s, kt[0].x);
-    BgKnot<R> c = kt[k];
-    while (c.x > s) c = kt[--k];
-    while (c.xn <= s) c = kt[++k];
+    s = max_r(s, x0);
+    if (c.x > s || c.xn <= s) {
+        while (c.x > s) c = kt[--k];
+        while (c.xn <= s) c = kt[++k];
+    }
     return fma_r(s - c.x, c.m, c.y);
 }
 
@@ -948,6 +950,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
     __syncthreads();
     const Pixel px = tile_pixel(p, xcd_tile(blockIdx.x, p.n_tiles));
     int k = 0;  // interval of the previous term
+    BgKnot<R> ck = kt[0];  // its record
+    const R x0 = ck.x;
     double acc64 = 0.0;
     float acc = 0.0f, accc = 0.0f;
     for (int u = 0; u < p.O; ++u)
@@ -964,7 +968,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
                         const double e0 = d[0] - src[SRC_DIR], e1 = d[1] - src[SRC_DIR + 1],
                                      e2 = d[2] - src[SRC_DIR + 2];
                         const double len = root_small(__builtin_fma(e2, e2, __builtin_fma(e1, e1, e0 * e0)));
-                        const double F = bg_curve(kt, k, len * src[SRC_HIL]);
+                        const double F = bg_curve(kt, ck, k, x0, len * src[SRC_HIL]);
                         const double P = bg_polarization(src, d, p.kahn);
                         sub = __builtin_fma(src[SRC_WEIGHT] * P, F * F, sub);
                     }
@@ -985,7 +989,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
                         const float e1 = (d32[1] - src32[SRC_DIR + 1]) + (dlo[1] - src32[SRC32_DIR_LO + 1]);
                         const float e2 = (d32[2] - src32[SRC_DIR + 2]) + (dlo[2] - src32[SRC32_DIR_LO + 2]);
                         const float len = root_small(__builtin_fmaf(e2, e2, __builtin_fmaf(e1, e1, e0 * e0)));
-                        const float F = bg_curve(kt, k, len * src32[SRC_HIL]);
+                        const float F = bg_curve(kt, ck, k, x0, len * src32[SRC_HIL]);
                         const float P = bg_polarization(src32, d32, (float)p.kahn);
                         kahn_add(s, c, src32[SRC_WEIGHT] * P * (F * F));
                     }
