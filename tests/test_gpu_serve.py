@@ -74,6 +74,29 @@ def test_served_equal_standalone_in_mix_and_alone(precision):
     srv.close()
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_served_gaussian_shape(precision):
+    """A server of the Gaussian shape (real N, the refinement crystal's
+    lattice form): every image equals the standalone Gaussian kernel's bit
+    for bit in the mix, and matches the oracle on one small shot."""
+    base, shots = small_served_shots(6, seed=61)
+    rng = np.random.default_rng(62)
+    shots = [s.replace(shape=synth.SHAPE_GAUSS, N=rng.uniform(5.0, 40.0, 3)) for s in shots]
+    fh = xrt.Fhkl.from_shot(base)
+    ref = [xrt.simulate(s, fh, precision=precision).cpu().numpy() for s in shots]
+    srv = xrt.Server(fh, hbm_budget=256 << 20, precision=precision, shape=xrt.XRT_SHAPE_GAUSS)
+    tickets = [srv.submit(s) for s in shots]
+    drain(srv, tickets)
+    for i, t in enumerate(tickets):
+        assert np.array_equal(srv.image(t).cpu().numpy(), ref[i]), f"shot {i} differs in the mix"
+        srv.release(t)
+    srv.close()
+    small = shots[0].replace(roi=(shots[0].roi[0], shots[0].roi[0] + 12, shots[0].roi[2], shots[0].roi[2] + 10))
+    r = compare(xrt.simulate(small, fh, precision=precision).cpu().numpy().astype(np.float64), o.simulate(small))
+    say("gauss served-shot oracle", precision, r)
+    assert r["zeros_ok"] and (r["max_rel"] <= 1e-12 if precision == "fp64" else r["floored"] <= 1e-5)
+
+
 def test_served_matches_oracle():
     base, shots = small_served_shots(3, seed=7, max_side=40)
     fh = xrt.Fhkl.from_shot(base)
