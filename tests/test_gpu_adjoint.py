@@ -93,6 +93,19 @@ def test_backward_matches_oracle_gradient():
         assert np.all(np.abs(g32[sl] - ref[sl]) <= 1e-4 * scale), (g32[sl], ref[sl])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_backward_binary32_residuals(precision):
+    """dL/dI given in binary32 is converted exactly: the gradient equals the
+    one from the same values in binary64, bit for bit."""
+    shot, origins, size = small_roi_case(n_roi=4)
+    fh = xrt.Fhkl.from_shot(shot)
+    g = _weights(4 * size[0] * size[1], seed=13).astype(np.float32).reshape(4, size[1], size[0])
+    g32 = torch.as_tensor(g, device="cuda")
+    a = xrt.backward_rois(shot, fh, origins, size, g32, precision).cpu().numpy()
+    b = xrt.backward_rois(shot, fh, origins, size, g32.double(), precision).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
 def test_backward_matches_finite_differences():
     """Central differences (step 1e-6 relative) of L = sum g I through the GPU
     forward against the GPU adjoint."""

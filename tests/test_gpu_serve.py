@@ -97,6 +97,23 @@ def test_served_gaussian_shape(precision):
     assert r["zeros_ok"] and (r["max_rel"] <= 1e-12 if precision == "fp64" else r["floored"] <= 1e-5)
 
 
+def test_served_binary64_images_of_mixed_sums():
+    """A mixed-precision server with binary64 images stores the same sums
+    the standalone kernel stores into a binary64 image."""
+    base, shots = small_served_shots(4, seed=63)
+    fh = xrt.Fhkl.from_shot(base)
+    srv = xrt.Server(fh, hbm_budget=256 << 20, precision="mixed", out_dtype="f64")
+    tickets = [srv.submit(s) for s in shots]
+    drain(srv, tickets)
+    for s, t in zip(shots, tickets):
+        img = srv.image(t)
+        assert img.dtype == torch.float64
+        ref = xrt.simulate(s, fh, precision="mixed", out_dtype=torch.float64)
+        assert torch.equal(img, ref)
+        srv.release(t)
+    srv.close()
+
+
 def test_served_matches_oracle():
     base, shots = small_served_shots(3, seed=7, max_side=40)
     fh = xrt.Fhkl.from_shot(base)
