@@ -247,9 +247,10 @@ typedef struct xrt_background {
 
 /* Background over the detector's region of interest, one kernel on `stream`.
  *  precision   XRT_FP64: every step in binary64.  XRT_MIXED: sample-point
- *              geometry and d - dir_j in binary64; |S|/2, the curve, P_j and
- *              the products in binary32; per-pixel sums compensated (Kahan)
- *              in binary32.
+ *              geometry in binary64; d - dir_j from binary32 heads and tails
+ *              of d and dir_j (exact where they nearly cancel, next to the
+ *              direct beam); |S|/2, the curve, P_j and the products in
+ *              binary32; per-pixel sums compensated (Kahan) in binary32.
  *  dev_image   device pointer, [roi rows][roi cols] of out_dtype.
  *  accumulate  0: overwrite; 1: add to the image (a background on top of
  *              xrt_simulate's spots, or several scatterers one after another).
