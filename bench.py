@@ -69,7 +69,7 @@ PEAK_OPS = 256 * 4 * 32 * 2.4e9
 # HBM bytes per binary64 launch from the FETCH_SIZE / WRITE_SIZE counters,
 # each scaled by what it reads for a 1 GiB device copy (profiles/
 # spots_full_shot_counters.txt); set to None whenever the kernel changes.
-TRAFFIC_FP64 = 50.16e6
+TRAFFIC_FP64 = 51.29e6
 
 
 def log(*a):
