@@ -110,6 +110,27 @@ def test_accumulate_onto_spots_and_between_scatterers():
     assert torch.equal(total, (spots + w) + a)
 
 
+def test_background_onto_served_images():
+    """A served shot's image, read in place, takes the background on the
+    device (accumulate) like a standalone image: the same bits."""
+    from tests.test_gpu_serve import drain, small_served_shots
+    base, shots = small_served_shots(3, seed=71)
+    fh = xrt.Fhkl.from_shot(base)
+    water = curve("water")
+    srv = xrt.Server(fh, hbm_budget=256 << 20, precision="mixed")
+    tickets = [srv.submit(s) for s in shots]
+    drain(srv, tickets)
+    for s, t in zip(shots, tickets):
+        img = srv.image(t, copy=False)
+        xrt.simulate_background(s, water, precision="mixed", out=img, accumulate=True)
+        ref = xrt.simulate(s, fh, precision="mixed")
+        xrt.simulate_background(s, water, precision="mixed", out=ref, accumulate=True)
+        torch.cuda.synchronize()
+        assert torch.equal(img, ref)
+        srv.release(t)
+    srv.close()
+
+
 def test_binary32_output_is_rounded_binary64():
     shot, bg = synth.tiny_shot(), curve("air")
     d = xrt.simulate_background(shot, bg, precision="fp64")
