@@ -106,6 +106,14 @@ int main(void)
     const double d[3] = {0.0, 0.6, 0.8}, inc[3] = {0.0, 0.0, 1.0}, e[3] = {1.0, 0.0, 0.0};
     CHECK(isfinite(xro_polarization(d, inc, e, 0.5)));
     CHECK(isfinite(xro_capture(1, 1e-4, 1.2e-4, 0.8)));
+    /* background: every branch of the curve (below, inside, at a knot, above) */
+    const double ks[4] = {0.0, 0.05, 0.1, 0.3}, kF[4] = {2.0, 2.6, 1.8, 1.1};
+    xro_bg bg = {4, ks, kF, 1e10};
+    CHECK(xro_bg_curve(&bg, -1.0) == 2.0 && xro_bg_curve(&bg, 0.05) == 2.6 && xro_bg_curve(&bg, 7.0) == 1.1);
+    CHECK(isfinite(xro_bg_curve(&bg, 0.07)));
+    double c[30];
+    CHECK(xro_background(&s, &bg, 30, pix, c, 2) == 0);
+    for (int k = 0; k < 30; ++k) CHECK(isfinite(c[k]) && c[k] > 0.0);
     printf("oracle checks passed under the sanitizers\n");
     return 0;
 }

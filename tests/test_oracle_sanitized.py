@@ -1,7 +1,8 @@
 """The oracle (oracle/xro.c) under AddressSanitizer and
 UndefinedBehaviorSanitizer: tests/oracle_check.c drives every entry point on
 small shots that reach every branch (sub-pixels, layers, off-axis sources,
-spindle steps, domains, table misses, both shapes, the gradient)."""
+spindle steps, domains, table misses, both shapes, the gradient, the
+background and every branch of its curve)."""
 import os
 import shutil
 import subprocess
