@@ -295,8 +295,15 @@ def serving_bench(n_cap=60, n_open=150, load=0.8):
     srv.close()
     log(f"serving: capacity {closed['images_per_s']:.1f} img/s ({closed['Gterm_per_s']:.0f} Gterm/s); "
         f"at {load:.2f} load p50 {opened['p50_ms']:.1f} ms p99 {opened['p99_ms']:.1f} ms")
+    # the same closed loop with the water-like background added to every image
+    srv = xrt.Server(fh, hbm_budget=16 << 30, max_resident=64, precision="mixed",
+                     background=synth.water_background())
+    serve.run_stream(srv, cap_shots[:2], np.zeros(2))
+    with_bg = serve.summarize(serve.run_stream(srv, cap_shots, np.zeros(n_cap)), cap_shots)
+    srv.close()
+    log(f"serving with the background: capacity {with_bg['images_per_s']:.1f} img/s")
     return {"workload": "served stream: log-uniform ROI, 1-100 sources, 1-200 domains, N in [5,40], mixed",
-            "closed_loop": closed, "poisson": opened, "load": load}
+            "closed_loop": closed, "poisson": opened, "load": load, "closed_loop_with_background": with_bg}
 
 
 def serving_io_bench(n_shots=40, write_ms=20.0, writers=4, budgets=(256 << 20, 64 << 20)):

@@ -307,6 +307,10 @@ xrt_status xrt_add_image(double *dev_acc, int32_t acc_nf, int32_t acc_ns, const 
  * memory thus never waits for a client that is still writing images out;
  * host memory does (finished shots are copied in finishing order as host
  * space frees up, each release making room).
+ *
+ * Background (desc.background): once a shot's spots are complete, the
+ * persistent kernel adds the server's scatterer to its image, in the server's
+ * precision, as xrt_simulate_background with accumulate would.
  * --------------------------------------------------------------------------- */
 typedef struct xrt_server xrt_server;
 
@@ -326,6 +330,11 @@ typedef struct xrt_server_desc {
     uint64_t host_budget;   /* pinned host bytes for written-out images: 0
                                (images read in place from the device arena)
                                or in [1 MiB, 1 TiB] */
+    const xrt_background *background; /* NULL, or a scatterer whose background
+                               every served image receives once its spots are
+                               complete (the image of xrt_simulate followed by
+                               xrt_simulate_background with accumulate, bit
+                               for bit); read during xrt_server_create only */
 } xrt_server_desc;
 
 enum { XRT_SHOT_QUEUED = 0, XRT_SHOT_RUNNING = 1, XRT_SHOT_DONE = 2 };

@@ -605,6 +605,25 @@ xrt_status served_descriptor(const xrt_detector *det, const xrt_beam *beam, cons
     return XRT_OK;
 }
 
+xrt_status check_background_desc(const xrt_background *bg) { return check_background(bg); }
+
+void background_rows(const xrt_background *bg, double *k64, float *k32)
+{
+    const int n = bg->n_knots;
+    for (int k = 0; k < n; ++k) {
+        k64[3 * k] = bg->stol[k];
+        k64[3 * k + 1] = bg->F[k];
+        k64[3 * k + 2] = k + 1 < n ? (bg->F[k + 1] - bg->F[k]) / (bg->stol[k + 1] - bg->stol[k]) : 0.0;
+        for (int c = 0; c < 3; ++c) k32[3 * k + c] = (float)k64[3 * k + c];
+    }
+}
+
+double background_norm(const xrt_detector *det, const xrt_beam *beam, double molecules)
+{
+    const double O = (double)det->oversample;
+    return R_E * R_E * beam->fluence * molecules / (O * O);
+}
+
 int32_t split_of(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal)
 {
     const int64_t nf = det->roi_f1 - det->roi_f0, ns = det->roi_s1 - det->roi_s0;
@@ -719,12 +738,7 @@ xrt_status xrt_simulate_background(const xrt_detector *det, const xrt_beam *beam
     double *k64 = host.data() + o_k64;
     float *s32 = reinterpret_cast<float *>(host.data() + o_s32);
     float *k32 = reinterpret_cast<float *>(host.data() + o_k32);
-    for (int k = 0; k < n; ++k) {
-        k64[3 * k] = bg->stol[k];
-        k64[3 * k + 1] = bg->F[k];
-        k64[3 * k + 2] = k + 1 < n ? (bg->F[k + 1] - bg->F[k]) / (bg->stol[k + 1] - bg->stol[k]) : 0.0;
-        for (int c = 0; c < 3; ++c) k32[3 * k + c] = (float)k64[3 * k + c];
-    }
+    xrt::host::background_rows(bg, k64, k32);
     for (int j = 0; j < n_src; ++j) {
         const double *row = host.data() + xrt::SRC_STRIDE * (size_t)j;
         float *r32 = s32 + xrt::SRC32_STRIDE * (size_t)j;
@@ -744,8 +758,7 @@ xrt_status xrt_simulate_background(const xrt_detector *det, const xrt_beam *beam
     p.n_roi = 1;
     p.n_tiles = p.tiles_per_roi;
     p.split = 1;
-    const double O = (double)det->oversample;
-    p.norm = R_E * R_E * beam->fluence * bg->molecules / (O * O);
+    p.norm = xrt::host::background_norm(det, beam, bg->molecules);
     p.image = dev_image;
     p.out_f64 = out_dtype == XRT_F64;
     p.accumulate = accumulate;

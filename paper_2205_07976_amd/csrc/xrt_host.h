@@ -27,6 +27,14 @@ xrt_status served_descriptor(const xrt_detector *det, const xrt_beam *beam, cons
 // xrt_simulate applies; 1 = whole sums).
 int32_t split_of(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal);
 
+// Background of an amorphous scatterer: validation; the curve as rows
+// (stol_k, F_k, slope_k; slope 0 at the last knot) in binary64 and their
+// binary32 copies ([n][3] each, as the kernels stage them); the
+// normalisation r_e^2 fluence molecules / O^2 of a validated shot.
+xrt_status check_background_desc(const xrt_background *bg);
+void background_rows(const xrt_background *bg, double *k64, float *k32);
+double background_norm(const xrt_detector *det, const xrt_beam *beam, double molecules);
+
 // Device tables of a structure-factor handle.
 void fhkl_tables(const xrt_fhkl *t, const double **F2_64, const float **F2_32, uint32_t *bytes64,
                  uint32_t *bytes32);

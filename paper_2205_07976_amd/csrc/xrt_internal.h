@@ -88,7 +88,7 @@ constexpr int SERVE_MAX_ROT = 256;   // spindle steps x mosaic domains per serve
 constexpr int SERVE_MAX_SRC = 128;   // sources per served shot
 constexpr int SERVE_MAX_CHUNK = 64;  // tiles (or tile parts) per chunk
 constexpr int SERVE_MAX_SPLIT = 64;  // parts per pixel sum
-enum { CHUNK_COMPUTE = 0, CHUNK_REDUCE = 1 };
+enum { CHUNK_COMPUTE = 0, CHUNK_REDUCE = 1, CHUNK_BACKGROUND = 2 };
 
 struct ShotDesc {
     Params p;               // pointer fields unused
@@ -101,6 +101,7 @@ struct ShotDesc {
     int32_t roi_f0, roi_s0;
     int32_t clamp;          // 0: every rint(h) of the shot is proven inside the padded table
     int32_t pad2;
+    double bg_norm;         // r_e^2 fluence molecules / O^2 of the server's background
 };
 
 struct ServeChunk {         // written by the host before the tail publishes it
@@ -110,7 +111,8 @@ struct ServeChunk {         // written by the host before the tail publishes it
     uint32_t shot;          // the shot's serial number (nonzero): with desc_off it
                             // names the descriptor a workgroup may keep in LDS
     int32_t kind;           // CHUNK_COMPUTE: units tile * split + part;
-                            // CHUNK_REDUCE: tiles whose parts are all done
+                            // CHUNK_REDUCE: tiles whose parts are all done;
+                            // CHUNK_BACKGROUND: tiles of a complete image
     int32_t pad;
 };
 
@@ -137,6 +139,8 @@ struct ServeArgs {
     const float *F2_32;
     uint32_t bytes64, bytes32;
     uint64_t idle_ticks;      // 100 MHz ticks of device-wide idleness before the kernel exits
+    const void *bg_knots;     // the background's curve records (BgKnot of the server's
+                              // precision, device memory), or null: no background
 };
 
 // Background of an amorphous scatterer over one region of interest: the

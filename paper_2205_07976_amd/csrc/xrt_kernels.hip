@@ -415,6 +415,175 @@ hipError_t launch_spots(const Params &p, int precision, bool clamp, hipStream_t 
 }
 
 // ---------------------------------------------------------------------------
+// Background of an amorphous scatterer (section III's second kernel: the air
+// and water around the crystal).  Per term (sample point, source):
+// stol = |d - dir| / (2 lambda), the scattering curve F at stol, and
+// w P F^2; no spindle or mosaic loop and no table gather, so it is a short
+// VALU-bound kernel with the spots kernel's pixel layout (one pixel per lane,
+// a 16 x 16 tile per workgroup).  The curve is staged in LDS as one record
+// per interval.  The source loop is unrolled by two, so the scalar loads of
+// the next source row overlap the current term.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double max_r(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ float max_r(float a, float b) { return __builtin_fmaxf(a, b); }
+
+// |d - dir| from its square x in [0, 4] (unit vectors), within an ulp or two
+// rather than correctly rounded (the curve is continuous, so this moves F by
+// as little).  binary64: the hardware reciprocal square root y of
+// x + 2^-1000 (the bias keeps x = 0 finite and is far below half an ulp of
+// any nonzero x met here), one Goldschmidt step on (x y, y / 2) and one
+// Newton correction of the root.  binary32: the hardware square root.
+__device__ __forceinline__ double root_small(double x)
+{
+    x += 0x1p-1000;
+    const double y = __builtin_amdgcn_rsq(x);
+    double s = x * y, h = 0.5 * y;
+    const double r = __builtin_fma(-h, s, 0.5);
+    s = __builtin_fma(s, r, s);
+    h = __builtin_fma(h, r, h);
+    return __builtin_fma(__builtin_fma(-s, s, x), h, s);
+}
+__device__ __forceinline__ float root_small(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// One interval of the curve in LDS: its knot, the next knot (NaN after the
+// last), F and the slope (0 after the last knot: constant beyond it).
+template <typename R>
+struct alignas(4 * sizeof(R)) BgKnot {
+    R x, xn, y, m;
+};
+// The curve at s.  The lane keeps the record c of its previous term's
+// interval k in registers; successive terms of a pixel (sources of nearby
+// wavelength, neighbouring sub-pixels) nearly always stay in it, so a lookup
+// is two compares and no LDS read.  Otherwise it walks through the LDS
+// records: down while the knot is above s, then up while the next knot is at
+// or below s.  s is clamped to the first knot x0, so the downward walk stops
+// at 0; the NaN after the last knot compares false, so the upward walk stops
+// at n - 1.
+template <typename R>
+__device__ __forceinline__ R bg_curve(const BgKnot<R> *kt, BgKnot<R> &c, int &k, R x0, R s)
+{
+    s = max_r(s, x0);
+    if (c.x > s || c.xn <= s) {
+        while (c.x > s) c = kt[--k];
+        while (c.xn <= s) c = kt[++k];
+    }
+    return fma_r(s - c.x, c.m, c.y);
+}
+
+// Kahn factor of one source row (binary64 or binary32 copy), P =
+// (1 + c^2 - K (x^2 - y^2)) / 2 as in the spots kernel, by fused products.
+template <typename R>
+__device__ __forceinline__ R bg_polarization(const R *src, const R d[3], R K)
+{
+    const R c = fma_r(d[2], src[SRC_DIR + 2], fma_r(d[1], src[SRC_DIR + 1], d[0] * src[SRC_DIR]));
+    const R x = fma_r(d[2], src[SRC_E + 2], fma_r(d[1], src[SRC_E + 1], d[0] * src[SRC_E]));
+    const R y = fma_r(d[2], src[SRC_B + 2], fma_r(d[1], src[SRC_B + 1], d[0] * src[SRC_B]));
+    return R(0.5) * fma_r(-K, fma_r(x, x, -(y * y)), fma_r(c, c, R(1)));
+}
+
+template <int PREC>
+using BgReal = typename std::conditional<PREC == XRT_FP64, double, float>::type;
+
+// The background sum of pixel (i_f, i_s), not normalised: the loops over
+// sub-pixels, layers and sources of the standalone and the served kernels
+// alike (kt: the curve records, in LDS or global memory; srcs and srcs32: the
+// binary64 rows and their binary32 copies with direction tails), so a pixel
+// has the same bits through either.
+template <int PREC>
+__device__ __forceinline__ double bg_pixel_sum(const Params &p, const BgKnot<BgReal<PREC>> *kt, const double *srcs,
+                                               const float *srcs32, int i_f, int i_s)
+{
+    using R = BgReal<PREC>;
+    int k = 0;              // interval of the previous term
+    BgKnot<R> ck = kt[0];   // its record
+    const R x0 = ck.x;
+    double acc64 = 0.0;
+    float acc = 0.0f, accc = 0.0f;
+    for (int u = 0; u < p.O; ++u)
+        for (int v = 0; v < p.O; ++v)
+            for (int t = 0; t < p.T; ++t) {
+                double d[3], dist;
+                sample_dir(p, i_f, i_s, u, v, t, d, dist);
+                const double wgeo = sample_weight(p, d, dist, t);
+                if constexpr (PREC == XRT_FP64) {
+                    double sub = 0.0;
+#pragma unroll 2
+                    for (int j = 0; j < p.n_src; ++j) {
+                        const double *src = srcs + SRC_STRIDE * j;
+                        const double e0 = d[0] - src[SRC_DIR], e1 = d[1] - src[SRC_DIR + 1],
+                                     e2 = d[2] - src[SRC_DIR + 2];
+                        const double len = root_small(__builtin_fma(e2, e2, __builtin_fma(e1, e1, e0 * e0)));
+                        const double F = bg_curve(kt, ck, k, x0, len * src[SRC_HIL]);
+                        const double P = bg_polarization(src, d, p.kahn);
+                        sub = __builtin_fma(src[SRC_WEIGHT] * P, F * F, sub);
+                    }
+                    acc64 = __builtin_fma(wgeo, sub, acc64);
+                } else {
+                    // d - dir cancels near the direct beam: d and dir are
+                    // each split into a binary32 head and the binary32 rest,
+                    // the heads subtract exactly there (Sterbenz), and the
+                    // rests add back what binary64 would have kept
+                    const float d32[3] = {(float)d[0], (float)d[1], (float)d[2]};
+                    const float dlo[3] = {(float)(d[0] - (double)d32[0]), (float)(d[1] - (double)d32[1]),
+                                          (float)(d[2] - (double)d32[2])};
+                    float s = 0.0f, c = 0.0f;
+#pragma unroll 2
+                    for (int j = 0; j < p.n_src; ++j) {
+                        const float *src32 = srcs32 + SRC32_STRIDE * j;
+                        const float e0 = (d32[0] - src32[SRC_DIR]) + (dlo[0] - src32[SRC32_DIR_LO]);
+                        const float e1 = (d32[1] - src32[SRC_DIR + 1]) + (dlo[1] - src32[SRC32_DIR_LO + 1]);
+                        const float e2 = (d32[2] - src32[SRC_DIR + 2]) + (dlo[2] - src32[SRC32_DIR_LO + 2]);
+                        const float len = root_small(__builtin_fmaf(e2, e2, __builtin_fmaf(e1, e1, e0 * e0)));
+                        const float F = bg_curve(kt, ck, k, x0, len * src32[SRC_HIL]);
+                        const float P = bg_polarization(src32, d32, (float)p.kahn);
+                        kahn_add(s, c, src32[SRC_WEIGHT] * P * (F * F));
+                    }
+                    kahn_add(acc, accc, (float)wgeo * (s - c));
+                }
+            }
+    return PREC == XRT_FP64 ? acc64 : (double)(acc - accc);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void background_kernel(const BgParams b)
+{
+    using R = BgReal<PREC>;
+    extern __shared__ double bg_lds[];
+    const Params &p = b.p;
+    BgKnot<R> *kt = reinterpret_cast<BgKnot<R> *>(bg_lds);  // [n]
+    const R *kn;
+    if constexpr (PREC == XRT_FP64)
+        kn = b.knots64;
+    else
+        kn = b.knots32;
+    for (int i = threadIdx.x; i < b.n_knots; i += BLOCK) {
+        BgKnot<R> c;
+        c.x = kn[3 * i];
+        c.xn = i + 1 < b.n_knots ? kn[3 * i + 3] : R(NAN);
+        c.y = kn[3 * i + 1];
+        c.m = kn[3 * i + 2];
+        kt[i] = c;
+    }
+    __syncthreads();
+    const Pixel px = tile_pixel(p, xcd_tile(blockIdx.x, p.n_tiles));
+    const double sum = bg_pixel_sum<PREC>(p, kt, p.src, b.src32, px.i_f, px.i_s);
+    if (px.live) store_pixel(p, px.out, p.norm * sum);
+}
+
+hipError_t launch_background(const BgParams &b, int precision, hipStream_t stream)
+{
+    const dim3 grid(b.p.n_tiles), block(BLOCK);
+    const size_t n = 4 * (size_t)b.n_knots;
+    if (precision == XRT_FP64)
+        hipLaunchKernelGGL(background_kernel<XRT_FP64>, grid, block, n * sizeof(double), stream, b);
+    else
+        hipLaunchKernelGGL(background_kernel<XRT_MIXED>, grid, block, n * sizeof(float), stream, b);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Persistent served-shot kernel (continuous batching).  Workgroups claim
 // chunks of tiles from the published ring (a compare-and-swap on the claim
 // counter, only below the published tail), stage the chunk's shot descriptor
@@ -507,6 +676,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     __shared__ ShotDesc sd;
     __shared__ double smats[9 * SERVE_MAX_ROT];
     __shared__ double ssrc[SRC_STRIDE * SERVE_MAX_SRC];
+    __shared__ float ssrc32[SRC32_STRIDE * SERVE_MAX_SRC];  // background chunks, mixed
     __shared__ long long s_claim;
     __shared__ uint64_t s_off, s_have_off;
     __shared__ int32_t s_tile0, s_ntiles, s_kind;
@@ -608,6 +778,23 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
         const int split = p.split;
         const int n_outer = p.O * p.O * p.T * p.n_src;
         const uint64_t img = sd.image_off, part = sd.partial_off;
+        if (PREC == XRT_MIXED && s_kind == CHUNK_BACKGROUND) {
+            // binary32 copies of the source rows with direction tails, made
+            // as the host makes them for the standalone background kernel
+            for (int i = threadIdx.x; i < p.n_src * SRC32_STRIDE; i += BLOCK) {
+                const int j = i / SRC32_STRIDE, q = i - j * SRC32_STRIDE;
+                const double *row = ssrc + SRC_STRIDE * j;
+                float v = 0.0f;
+                if (q < SRC_STRIDE) {
+                    v = (float)row[q];
+                } else if (q >= SRC32_DIR_LO && q < SRC32_DIR_LO + 3) {
+                    const double x = row[SRC_DIR + q - SRC32_DIR_LO];
+                    v = (float)(x - (double)(float)x);
+                }
+                ssrc32[i] = v;
+            }
+            __syncthreads();
+        }
         for (int i = 0; i < n_units; ++i) {
             // compute chunk: unit = tile * split + part; reduce chunk: unit = tile
             const int unit = s_tile0 + i;
@@ -622,6 +809,28 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
             const uint64_t pq = part + 8 * (((uint64_t)t * split) * BLOCK + threadIdx.x);
             const bool parts_ok = part <= a.arena_bytes && pq + 8 * ((uint64_t)(split - 1) * BLOCK + 1) <= a.arena_bytes &&
                                   8 * (((uint64_t)t * split + split) * BLOCK) <= sd.partial_bytes;
+            if (s_kind == CHUNK_BACKGROUND) {
+                // the server's background added into the complete image, as
+                // xrt_simulate_background with accumulate does
+                if (!a.bg_knots) continue;
+                const int i_f = roi_f0 + (lf < p.roi_nf ? lf : p.roi_nf - 1);
+                const int i_s = roi_s0 + (ls < p.roi_ns ? ls : p.roi_ns - 1);
+                const double bsum = bg_pixel_sum<PREC>(p, static_cast<const BgKnot<BgReal<PREC>> *>(a.bg_knots), ssrc,
+                                                       ssrc32, i_f, i_s);
+                const double bval = uni(sd.bg_norm) * bsum;
+                const uint64_t besz = p.out_f64 ? 8 : 4;
+                const uint64_t bo = besz * ((uint64_t)ls * (uint64_t)p.roi_nf + (uint64_t)lf);
+                if (live && bo + besz <= sd.image_bytes && img <= a.arena_bytes && bo + besz <= a.arena_bytes - img) {
+                    if (p.out_f64) {
+                        double *q = reinterpret_cast<double *>(a.arena + img + bo);
+                        *q = *q + bval;
+                    } else {
+                        float *q = reinterpret_cast<float *>(a.arena + img + bo);
+                        *q = *q + (float)bval;
+                    }
+                }
+                continue;
+            }
             double sum;
             if (s_kind == CHUNK_COMPUTE) {
                 const int i_f = roi_f0 + (lf < p.roi_nf ? lf : p.roi_nf - 1);
@@ -855,159 +1064,6 @@ hipError_t launch_grad(const Params &p, int precision, bool clamp, const void *d
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(grad_reduce_kernel, dim3(1), dim3(BLOCK), 0, stream, partial, p.n_tiles, grad13, inv_scale);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Background of an amorphous scatterer (section III's second kernel: the air
-// and water around the crystal).  Per term (sample point, source):
-// stol = |d - dir| / (2 lambda), the scattering curve F at stol, and
-// w P F^2; no spindle or mosaic loop and no table gather, so it is a short
-// VALU-bound kernel with the spots kernel's pixel layout (one pixel per lane,
-// a 16 x 16 tile per workgroup).  The curve is staged in LDS as one record
-// per interval.  The source loop is unrolled by two, so the scalar loads of
-// the next source row overlap the current term.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double max_r(double a, double b) { return __builtin_fmax(a, b); }
-__device__ __forceinline__ float max_r(float a, float b) { return __builtin_fmaxf(a, b); }
-
-// |d - dir| from its square x in [0, 4] (unit vectors), within an ulp or two
-// rather than correctly rounded (the curve is continuous, so this moves F by
-// as little).  binary64: the hardware reciprocal square root y of
-// x + 2^-1000 (the bias keeps x = 0 finite and is far below half an ulp of
-// any nonzero x met here), one Goldschmidt step on (x y, y / 2) and one
-// Newton correction of the root.  binary32: the hardware square root.
-__device__ __forceinline__ double root_small(double x)
-{
-    x += 0x1p-1000;
-    const double y = __builtin_amdgcn_rsq(x);
-    double s = x * y, h = 0.5 * y;
-    const double r = __builtin_fma(-h, s, 0.5);
-    s = __builtin_fma(s, r, s);
-    h = __builtin_fma(h, r, h);
-    return __builtin_fma(__builtin_fma(-s, s, x), h, s);
-}
-__device__ __forceinline__ float root_small(float x) { return __builtin_amdgcn_sqrtf(x); }
-
-// One interval of the curve in LDS: its knot, the next knot (NaN after the
-// last), F and the slope (0 after the last knot: constant beyond it).
-template <typename R>
-struct alignas(4 * sizeof(R)) BgKnot {
-    R x, xn, y, m;
-};
-// The curve at s.  The lane keeps the record c of its previous term's
-// interval k in registers; successive terms of a pixel (sources of nearby
-// wavelength, neighbouring sub-pixels) nearly always stay in it, so a lookup
-// is two compares and no LDS read.  Otherwise it walks through the LDS
-// records: down while the knot is above s, then up while the next knot is at
-// or below s.  s is clamped to the first knot x0, so the downward walk stops
-// at 0; the NaN after the last knot compares false, so the upward walk stops
-// at n - 1.
-template <typename R>
-__device__ __forceinline__ R bg_curve(const BgKnot<R> *kt, BgKnot<R> &c, int &k, R x0, R s)
-{
-    s = max_r(s, x0);
-    if (c.x > s || c.xn <= s) {
-        while (c.x > s) c = kt[--k];
-        while (c.xn <= s) c = kt[++k];
-    }
-    return fma_r(s - c.x, c.m, c.y);
-}
-
-// Kahn factor of one source row (binary64 or binary32 copy), P =
-// (1 + c^2 - K (x^2 - y^2)) / 2 as in the spots kernel, by fused products.
-template <typename R>
-__device__ __forceinline__ R bg_polarization(const R *src, const R d[3], R K)
-{
-    const R c = fma_r(d[2], src[SRC_DIR + 2], fma_r(d[1], src[SRC_DIR + 1], d[0] * src[SRC_DIR]));
-    const R x = fma_r(d[2], src[SRC_E + 2], fma_r(d[1], src[SRC_E + 1], d[0] * src[SRC_E]));
-    const R y = fma_r(d[2], src[SRC_B + 2], fma_r(d[1], src[SRC_B + 1], d[0] * src[SRC_B]));
-    return R(0.5) * fma_r(-K, fma_r(x, x, -(y * y)), fma_r(c, c, R(1)));
-}
-
-template <int PREC>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void background_kernel(const BgParams b)
-{
-    using R = typename std::conditional<PREC == XRT_FP64, double, float>::type;
-    extern __shared__ double bg_lds[];
-    const Params &p = b.p;
-    BgKnot<R> *kt = reinterpret_cast<BgKnot<R> *>(bg_lds);  // [n]
-    const R *kn;
-    if constexpr (PREC == XRT_FP64)
-        kn = b.knots64;
-    else
-        kn = b.knots32;
-    for (int i = threadIdx.x; i < b.n_knots; i += BLOCK) {
-        BgKnot<R> c;
-        c.x = kn[3 * i];
-        c.xn = i + 1 < b.n_knots ? kn[3 * i + 3] : R(NAN);
-        c.y = kn[3 * i + 1];
-        c.m = kn[3 * i + 2];
-        kt[i] = c;
-    }
-    __syncthreads();
-    const Pixel px = tile_pixel(p, xcd_tile(blockIdx.x, p.n_tiles));
-    int k = 0;  // interval of the previous term
-    BgKnot<R> ck = kt[0];  // its record
-    const R x0 = ck.x;
-    double acc64 = 0.0;
-    float acc = 0.0f, accc = 0.0f;
-    for (int u = 0; u < p.O; ++u)
-        for (int v = 0; v < p.O; ++v)
-            for (int t = 0; t < p.T; ++t) {
-                double d[3], dist;
-                sample_dir(p, px.i_f, px.i_s, u, v, t, d, dist);
-                const double wgeo = sample_weight(p, d, dist, t);
-                if constexpr (PREC == XRT_FP64) {
-                    double sub = 0.0;
-#pragma unroll 2
-                    for (int j = 0; j < p.n_src; ++j) {
-                        const double *src = p.src + SRC_STRIDE * j;
-                        const double e0 = d[0] - src[SRC_DIR], e1 = d[1] - src[SRC_DIR + 1],
-                                     e2 = d[2] - src[SRC_DIR + 2];
-                        const double len = root_small(__builtin_fma(e2, e2, __builtin_fma(e1, e1, e0 * e0)));
-                        const double F = bg_curve(kt, ck, k, x0, len * src[SRC_HIL]);
-                        const double P = bg_polarization(src, d, p.kahn);
-                        sub = __builtin_fma(src[SRC_WEIGHT] * P, F * F, sub);
-                    }
-                    acc64 = __builtin_fma(wgeo, sub, acc64);
-                } else {
-                    // d - dir cancels near the direct beam: d and dir are
-                    // each split into a binary32 head and the binary32 rest,
-                    // the heads subtract exactly there (Sterbenz), and the
-                    // rests add back what binary64 would have kept
-                    const float d32[3] = {(float)d[0], (float)d[1], (float)d[2]};
-                    const float dlo[3] = {(float)(d[0] - (double)d32[0]), (float)(d[1] - (double)d32[1]),
-                                          (float)(d[2] - (double)d32[2])};
-                    float s = 0.0f, c = 0.0f;
-#pragma unroll 2
-                    for (int j = 0; j < p.n_src; ++j) {
-                        const float *src32 = b.src32 + SRC32_STRIDE * j;
-                        const float e0 = (d32[0] - src32[SRC_DIR]) + (dlo[0] - src32[SRC32_DIR_LO]);
-                        const float e1 = (d32[1] - src32[SRC_DIR + 1]) + (dlo[1] - src32[SRC32_DIR_LO + 1]);
-                        const float e2 = (d32[2] - src32[SRC_DIR + 2]) + (dlo[2] - src32[SRC32_DIR_LO + 2]);
-                        const float len = root_small(__builtin_fmaf(e2, e2, __builtin_fmaf(e1, e1, e0 * e0)));
-                        const float F = bg_curve(kt, ck, k, x0, len * src32[SRC_HIL]);
-                        const float P = bg_polarization(src32, d32, (float)p.kahn);
-                        kahn_add(s, c, src32[SRC_WEIGHT] * P * (F * F));
-                    }
-                    kahn_add(acc, accc, (float)wgeo * (s - c));
-                }
-            }
-    const double sum = PREC == XRT_FP64 ? acc64 : (double)(acc - accc);
-    if (px.live) store_pixel(p, px.out, p.norm * sum);
-}
-
-hipError_t launch_background(const BgParams &b, int precision, hipStream_t stream)
-{
-    const dim3 grid(b.p.n_tiles), block(BLOCK);
-    const size_t n = 4 * (size_t)b.n_knots;
-    if (precision == XRT_FP64)
-        hipLaunchKernelGGL(background_kernel<XRT_FP64>, grid, block, n * sizeof(double), stream, b);
-    else
-        hipLaunchKernelGGL(background_kernel<XRT_MIXED>, grid, block, n * sizeof(float), stream, b);
     return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ constexpr uint64_t ALIGN = 256;
 constexpr int TILE_PIXELS = 256;            // 16 x 16 pixels per tile
 constexpr uint64_t CHUNK_TERMS = 1u << 20;  // pixel-terms a compute chunk aims at
 constexpr int MAX_CHUNK = 64;               // work units per chunk
-enum { PHASE_COMPUTE = 0, PHASE_REDUCE = 1 };
+enum { PHASE_COMPUTE = 0, PHASE_REDUCE = 1, PHASE_BACKGROUND = 2 };
 enum { QUEUED = 0, RUNNING = 1, DONE = 2 };
 
 inline uint64_t align_up(uint64_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
@@ -79,11 +79,14 @@ struct Work {
     int32_t n_tiles = 0;           // 16 x 16 tiles of the region
     int32_t split = 1;             // parts per pixel sum (1: whole sums)
     uint64_t terms_per_pixel = 0;
+    uint64_t bg_terms_per_pixel = 0;  // > 0: a background phase over the tiles
+                                      // once the image is complete
     // owned by the scheduler
     int state = QUEUED;
     uint64_t dev_off = 0, host_off = 0;
     // current phase: PHASE_COMPUTE over units tile * split + part, then, for
-    // split sums, PHASE_REDUCE over tiles once every part is done
+    // split sums, PHASE_REDUCE over tiles once every part is done, then, with
+    // a background, PHASE_BACKGROUND over tiles once the image is complete
     int32_t phase = PHASE_COMPUTE;
     int32_t n_units = 0, chunk_units = 1, next_unit = 0;
     int64_t chunks_total = 0, chunks_done = 0;
@@ -180,7 +183,9 @@ class Scheduler {
             w.next_unit += c.n_units;
             // a reduce chunk reads K values per pixel: count it as K terms
             w.work_published += (double)c.n_units * TILE_PIXELS *
-                                (w.phase == PHASE_COMPUTE ? (double)w.terms_per_pixel / w.split : w.split);
+                                (w.phase == PHASE_COMPUTE  ? (double)w.terms_per_pixel / w.split
+                                 : w.phase == PHASE_REDUCE ? (double)w.split
+                                                           : (double)w.bg_terms_per_pixel);
             inflight_.push_back({c.seq, c.ticket});
             emit(c, w);
             ++n;
@@ -191,8 +196,9 @@ class Scheduler {
 
     // Finished chunks: is_done(seq) says whether chunk `seq` is done.  A
     // compute phase of a split shot that completes starts its reduce phase;
-    // any other completed phase finishes the shot, whose ticket is appended to
-    // *finished.
+    // the phase that completes the image starts the background phase of a
+    // shot that has one; any other completed phase finishes the shot, whose
+    // ticket is appended to *finished.
     template <class IsDone>
     void collect(IsDone is_done, std::vector<uint64_t> *finished)
     {
@@ -207,6 +213,9 @@ class Scheduler {
             if (++w.chunks_done == w.chunks_total) {
                 if (w.phase == PHASE_COMPUTE && w.split > 1) {
                     start_phase(w, PHASE_REDUCE);  // every part sum is in the arena
+                    admitted_.push_back(w.ticket);
+                } else if (w.phase != PHASE_BACKGROUND && w.bg_terms_per_pixel > 0) {
+                    start_phase(w, PHASE_BACKGROUND);  // the image is complete
                     admitted_.push_back(w.ticket);
                 } else {
                     w.state = DONE;
@@ -258,19 +267,21 @@ class Scheduler {
         uint64_t seq, ticket;
     };
 
-    // Chunking of a phase: compute chunks hold about CHUNK_TERMS pixel-terms
-    // (a few ms of one workgroup, so a shot admitted later waits at most that
-    // long for a workgroup, and the last chunks of a shot end close together)
-    // and no more units than spread the phase over every workgroup; reduce
-    // chunks (K loads per pixel) are spread the same way.
+    // Chunking of a phase: compute and background chunks hold about
+    // CHUNK_TERMS pixel-terms (a few ms of one workgroup, so a shot admitted
+    // later waits at most that long for a workgroup, and the last chunks of a
+    // shot end close together) and no more units than spread the phase over
+    // every workgroup; reduce chunks (K loads per pixel) are spread the same
+    // way.
     void start_phase(Work &w, int32_t phase)
     {
         w.phase = phase;
         w.n_units = phase == PHASE_COMPUTE ? w.n_tiles * w.split : w.n_tiles;
         const uint64_t by_spread = ((uint64_t)w.n_units + n_wg_ - 1) / n_wg_;
         uint64_t by_cost = (uint64_t)MAX_CHUNK;
-        if (phase == PHASE_COMPUTE) {
-            const uint64_t per_unit = std::max<uint64_t>(1, TILE_PIXELS * w.terms_per_pixel / (uint64_t)w.split);
+        if (phase != PHASE_REDUCE) {
+            const uint64_t tpp = phase == PHASE_COMPUTE ? w.terms_per_pixel / (uint64_t)w.split : w.bg_terms_per_pixel;
+            const uint64_t per_unit = std::max<uint64_t>(1, TILE_PIXELS * tpp);
             by_cost = std::max<uint64_t>(1, CHUNK_TERMS / per_unit);
         }
         w.chunk_units = (int32_t)std::max<uint64_t>(1, std::min<uint64_t>({by_cost, by_spread, (uint64_t)MAX_CHUNK}));

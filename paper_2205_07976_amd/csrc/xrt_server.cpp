@@ -55,7 +55,8 @@ namespace {
 
 using xrt::sched::align_up;
 constexpr uint32_t RING = 1u << 16;
-static_assert(xrt::sched::PHASE_COMPUTE == xrt::CHUNK_COMPUTE && xrt::sched::PHASE_REDUCE == xrt::CHUNK_REDUCE,
+static_assert(xrt::sched::PHASE_COMPUTE == xrt::CHUNK_COMPUTE && xrt::sched::PHASE_REDUCE == xrt::CHUNK_REDUCE &&
+                  xrt::sched::PHASE_BACKGROUND == xrt::CHUNK_BACKGROUND,
               "chunk kinds");
 static_assert(xrt::sched::MAX_CHUNK == xrt::SERVE_MAX_CHUNK, "units per chunk");
 static_assert(xrt::sched::TILE_PIXELS == 256, "tile of the kernels");
@@ -104,6 +105,10 @@ struct xrt_server {
     char *out = nullptr;
     xrt::sched::Arena *out_arena = nullptr;
     hipStream_t copy = nullptr;
+    // background (desc.background): the curve as BgKnot records of the
+    // server's precision in device memory, and the molecule count
+    void *bg_knots = nullptr;
+    double bg_molecules = 0.0;
     std::deque<uint64_t> to_copy;
     std::vector<uint64_t> copying;
     std::vector<hipEvent_t> spare_events;
@@ -134,6 +139,7 @@ xrt_status check_desc(const xrt_server_desc *d)
     if (!(d->idle_exit_us >= 1.0 && d->idle_exit_us <= 1e6)) return fail(XRT_ERANGE, "idle_exit_us must be in [1, 1e6]");
     if (d->host_budget != 0 && (d->host_budget < (1u << 20) || d->host_budget > ((uint64_t)1 << 40)))
         return fail(XRT_ERANGE, "host_budget must be 0 or in [1 MiB, 1 TiB]");
+    if (d->background) return xrt::host::check_background_desc(d->background);
     return XRT_OK;
 }
 
@@ -145,6 +151,7 @@ void free_server(xrt_server *s)
     for (hipEvent_t e : s->spare_events) (void)hipEventDestroy(e);
     if (s->copy) (void)hipStreamDestroy(s->copy);
     if (s->out) (void)hipHostFree(s->out);
+    if (s->bg_knots) (void)hipFree(s->bg_knots);
     delete s->out_arena;
     if (s->kernel_done) (void)hipEventDestroy(s->kernel_done);
     if (s->work) (void)hipStreamDestroy(s->work);
@@ -279,6 +286,7 @@ xrt_status admit(xrt_server *s)
         d.image_bytes = sh.image_bytes;
         d.partial_off = w.dev_off + align_up(sh.image_bytes);
         d.partial_bytes = sh.part_bytes;
+        d.bg_norm = s->bg_knots ? xrt::host::background_norm(&sh.det, &sh.beam, s->bg_molecules) : 0.0;
         std::memcpy(s->host_arena + w.host_off, &d, sizeof d);
         std::memcpy(s->host_arena + w.host_off + d.mats_rel, host.data(), sizeof(double) * host.size());
         sh.t_admit = s->now();
@@ -324,6 +332,7 @@ xrt_status launch(xrt_server *s)
     a.arena_bytes = s->desc.hbm_budget;
     xrt::host::fhkl_tables(s->fhkl, &a.F2_64, &a.F2_32, &a.bytes64, &a.bytes32);
     a.idle_ticks = (uint64_t)(s->desc.idle_exit_us * 100.0);  // s_memrealtime: 100 MHz
+    a.bg_knots = s->bg_knots;
     // a new kernel starts with no busy workgroup, no exit flag, no finished chunk
     hipError_t e = hipMemsetAsync(s->dev_ctl + 1, 0, 2 * sizeof(unsigned long long), s->work);
     if (e == hipSuccess) e = xrt::launch_serve(a, s->desc.precision, s->desc.shape, s->n_wg, s->work);
@@ -369,6 +378,31 @@ xrt_status xrt_server_create(const xrt_server_desc *desc, const xrt_fhkl *fhkl, 
     if (e == hipSuccess && desc->host_budget) {
         e = hipHostMalloc((void **)&s->out, desc->host_budget, hipHostMallocDefault);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
+    }
+    if (e == hipSuccess && desc->background) {
+        // one record per interval (knot, next knot or NaN, F, slope), the
+        // values the standalone background kernel stages from the same rows
+        const int n = desc->background->n_knots;
+        std::vector<double> k64(3 * (size_t)n), r64(4 * (size_t)n);
+        std::vector<float> k32(3 * (size_t)n), r32(4 * (size_t)n);
+        xrt::host::background_rows(desc->background, k64.data(), k32.data());
+        for (int k = 0; k < n; ++k) {
+            r64[4 * k] = k64[3 * k];
+            r64[4 * k + 1] = k + 1 < n ? k64[3 * k + 3] : std::nan("");
+            r64[4 * k + 2] = k64[3 * k + 1];
+            r64[4 * k + 3] = k64[3 * k + 2];
+            r32[4 * k] = k32[3 * k];
+            r32[4 * k + 1] = k + 1 < n ? k32[3 * k + 3] : std::nanf("");
+            r32[4 * k + 2] = k32[3 * k + 1];
+            r32[4 * k + 3] = k32[3 * k + 2];
+        }
+        const bool f64 = desc->precision == XRT_FP64;
+        const size_t bytes = f64 ? sizeof(double) * r64.size() : sizeof(float) * r32.size();
+        e = hipMalloc(&s->bg_knots, bytes);
+        if (e == hipSuccess)
+            e = hipMemcpy(s->bg_knots, f64 ? (const void *)r64.data() : (const void *)r32.data(), bytes,
+                          hipMemcpyHostToDevice);
+        s->bg_molecules = desc->background->molecules;
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->kernel_done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -432,6 +466,8 @@ xrt_status xrt_server_submit(xrt_server *s, const xrt_detector *det, const xrt_b
     w.n_tiles = (int32_t)(((det->roi_f1 - det->roi_f0 + 15) / 16) * ((det->roi_s1 - det->roi_s0 + 15) / 16));
     w.terms_per_pixel = (uint64_t)det->oversample * det->oversample * det->n_layers * (uint64_t)beam->n_src *
                         (uint64_t)xtal->n_phi * xtal->n_mos;
+    if (s->bg_knots)  // the server's background, a phase after the sums
+        w.bg_terms_per_pixel = (uint64_t)det->oversample * det->oversample * det->n_layers * (uint64_t)beam->n_src;
     sh.part_bytes = w.split > 1 ? sizeof(double) * (uint64_t)w.n_tiles * (uint64_t)w.split * xrt::sched::TILE_PIXELS : 0;
     w.footprint = align_up(sh.image_bytes) + align_up(sh.part_bytes);
     if (w.footprint > s->desc.hbm_budget)

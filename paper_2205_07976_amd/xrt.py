@@ -80,6 +80,7 @@ class ServerDesc(C.Structure):
         ("struct_size", C.c_uint32), ("hbm_budget", C.c_uint64), ("max_resident", C.c_int32),
         ("precision", C.c_int32), ("shape", C.c_int32), ("out_dtype", C.c_int32),
         ("workgroups", C.c_int32), ("idle_exit_us", C.c_double), ("host_budget", C.c_uint64),
+        ("background", C.c_void_p),
     ]
 
 
@@ -402,12 +403,19 @@ class Server:
     a torch tensor viewing the server's arena (copy it before release)."""
 
     def __init__(self, fhkl: Fhkl, hbm_budget=8 << 30, max_resident=256, precision="mixed",
-                 shape=XRT_SHAPE_SINCG, out_dtype=None, workgroups=0, idle_exit_us=5000.0, host_budget=0):
+                 shape=XRT_SHAPE_SINCG, out_dtype=None, workgroups=0, idle_exit_us=5000.0, host_budget=0,
+                 background=None):
         self.fhkl = fhkl  # kept alive: the server borrows its tables
         self.out_f64 = (out_dtype == "f64") if out_dtype else precision == "fp64"
         self.writes_out = bool(host_budget)
+        bg = None
+        if background is not None:  # copied by xrt_server_create
+            x, F = _arr(background.stol), _arr(background.F)
+            bg = BackgroundDesc(C.sizeof(BackgroundDesc), len(x), x.ctypes.data_as(_pd), F.ctypes.data_as(_pd),
+                                float(background.molecules))
         d = ServerDesc(C.sizeof(ServerDesc), int(hbm_budget), int(max_resident), _PREC[precision], int(shape),
-                       XRT_F64 if self.out_f64 else XRT_F32, int(workgroups), float(idle_exit_us), int(host_budget))
+                       XRT_F64 if self.out_f64 else XRT_F32, int(workgroups), float(idle_exit_us), int(host_budget),
+                       C.cast(C.pointer(bg), C.c_void_p) if bg is not None else None)
         h = C.c_void_p()
         _check(load().xrt_server_create(C.byref(d), fhkl.handle, C.byref(h)))
         self._h = h

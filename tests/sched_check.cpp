@@ -23,9 +23,10 @@ using namespace xrt::sched;
     } while (0)
 
 static Work shot(uint64_t ticket, uint64_t footprint, int32_t n_tiles, uint64_t tpp, int32_t split = 1,
-                 uint64_t desc = 4096)
+                 uint64_t desc = 4096, uint64_t bg_tpp = 0)
 {
     Work w;
+    w.bg_terms_per_pixel = bg_tpp;
     w.ticket = ticket;
     w.footprint = footprint;
     w.desc_bytes = desc;
@@ -48,10 +49,15 @@ struct Device {
     size_t publish()
     {
         return s.publish([&](const Chunk &c, const Work &) {
-            // a reduce chunk comes only after every compute chunk of its shot is done
+            // a reduce chunk comes only after every compute chunk of its shot
+            // is done, a background chunk only after every compute and reduce
+            // chunk
             if (c.kind == PHASE_REDUCE)
                 for (const Chunk &x : log)
                     if (x.ticket == c.ticket && x.kind == PHASE_COMPUTE) CHECK(done.count(x.seq));
+            if (c.kind == PHASE_BACKGROUND)
+                for (const Chunk &x : log)
+                    if (x.ticket == c.ticket && x.kind != PHASE_BACKGROUND) CHECK(done.count(x.seq));
             pending.push_back(c);
             log.push_back(c);
         });
@@ -161,7 +167,7 @@ static void check_fifo_admission()
 
 static void check_units_and_depth()
 {
-    printf("chunks: every unit of every phase exactly once, depth bound, split phases in order\n");
+    printf("chunks: every unit of every phase exactly once, depth bound, phases in order\n");
     Scheduler s(1 << 30, 1 << 22, 64, 16, 1 << 16);
     Device d(s);
     std::map<uint64_t, Work> shots;
@@ -170,7 +176,8 @@ static void check_units_and_depth()
         const int32_t tiles = 1 + (int32_t)(rng() % 300);
         const uint64_t tpp = 1 + rng() % 200000;
         const int32_t split = (rng() % 3 == 0) ? 1 + (int32_t)(rng() % 64) : 1;
-        shots[k] = shot(k, 4096, tiles, tpp, split);
+        const uint64_t bg = (rng() % 2 == 0) ? 1 + rng() % 2000 : 0;
+        shots[k] = shot(k, 4096, tiles, tpp, split, 4096, bg);
         s.submit(shots[k]);
     }
     std::map<uint64_t, int> finished;
@@ -185,11 +192,13 @@ static void check_units_and_depth()
     for (auto &f : finished) CHECK(f.second == 1);
     // coverage per (shot, phase)
     std::map<std::pair<uint64_t, int>, std::vector<int>> cover;
-    std::map<uint64_t, uint64_t> last_compute, first_reduce;
+    std::map<uint64_t, uint64_t> last_compute, first_reduce, last_sums, first_bg;
     for (const Chunk &c : d.log) {
         auto &v = cover[{c.ticket, c.kind}];
         const Work &w = shots[c.ticket];
         const int n = c.kind == PHASE_COMPUTE ? w.n_tiles * w.split : w.n_tiles;
+        if (c.kind != PHASE_BACKGROUND) last_sums[c.ticket] = std::max(last_sums[c.ticket], c.seq);
+        if (c.kind == PHASE_BACKGROUND && !first_bg.count(c.ticket)) first_bg[c.ticket] = c.seq;
         if (v.empty()) v.assign(n, 0);
         CHECK(c.n_units >= 1 && c.n_units <= MAX_CHUNK && c.unit0 >= 0 && c.unit0 + c.n_units <= n);
         for (int u = c.unit0; u < c.unit0 + c.n_units; ++u) v[u]++;
@@ -205,6 +214,13 @@ static void check_units_and_depth()
             CHECK(first_reduce[w.ticket] > last_compute[w.ticket]);
         } else {
             CHECK(!cover.count({w.ticket, PHASE_REDUCE}));
+        }
+        if (w.bg_terms_per_pixel > 0) {
+            CHECK(cover.count({w.ticket, PHASE_BACKGROUND}));
+            for (int x : cover[{w.ticket, PHASE_BACKGROUND}]) CHECK(x == 1);
+            CHECK(first_bg[w.ticket] > last_sums[w.ticket]);
+        } else {
+            CHECK(!cover.count({w.ticket, PHASE_BACKGROUND}));
         }
     }
     for (auto &kv : shots) CHECK(s.release(kv.first));

@@ -131,6 +131,37 @@ def test_background_onto_served_images():
     srv.close()
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_served_with_background(precision):
+    """A server with a background: every image is the standalone spots image
+    plus the standalone background (accumulate), bit for bit, in a mix that
+    holds split shots (whose background follows their reduction); also
+    written out to host memory."""
+    from tests.test_gpu_serve import drain, small_served_shots
+    base, shots = small_served_shots(6, seed=81)
+    big = synth.served_shot(np.random.default_rng(82), base.F, base.hkl_min)
+    f0, s0 = big.roi[0], big.roi[2]
+    shots.append(big.replace(roi=(f0, min(f0 + 40, 2463), s0, min(s0 + 40, 2527))))  # split sums
+    fh = xrt.Fhkl.from_shot(base)
+    water = curve("water")
+    refs = []
+    for s in shots:
+        r = xrt.simulate(s, fh, precision=precision)
+        xrt.simulate_background(s, water, precision=precision, out=r, accumulate=True)
+        refs.append(r)
+    for host_budget in (0, 64 << 20):
+        srv = xrt.Server(fh, hbm_budget=256 << 20, precision=precision, host_budget=host_budget, background=water)
+        tickets = [srv.submit(s) for s in shots]
+        drain(srv, tickets)
+        for i, t in enumerate(tickets):
+            if host_budget:
+                assert np.array_equal(srv.host_image(t), refs[i].cpu().numpy()), i
+            else:
+                assert torch.equal(srv.image(t), refs[i]), i
+            srv.release(t)
+        srv.close()
+
+
 def test_binary32_output_is_rounded_binary64():
     shot, bg = synth.tiny_shot(), curve("air")
     d = xrt.simulate_background(shot, bg, precision="fp64")
