@@ -239,3 +239,19 @@ def test_server_desc_host_budget_range():
                            0, 5000.0, budget)
         assert lib.xrt_server_create(C.byref(d), C.c_void_p(8), C.byref(h)) == xrt.XRT_ERANGE
         assert "host_budget" in err()
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """With libxrt.so absent the binding raises instead of falling back to
+    anything else (there is no CPU path in the product)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2205_07976_amd import xrt\n"
+            "xrt.LIB_PATH = %r\n"
+            "try:\n"
+            "    xrt.load()\n"
+            "except ImportError as e:\n"
+            "    print('raised', e)\n" % (ROOT, str(tmp_path / "libxrt.so")))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "raised" in r.stdout and "missing" in r.stdout, r.stdout + r.stderr
