@@ -279,6 +279,18 @@ xrt_status xrt_add_image(double *dev_acc, int32_t acc_nf, int32_t acc_ns, const 
                          int32_t img_dtype, int32_t img_nf, int32_t img_ns, int32_t f0, int32_t s0,
                          void *stream);
 
+/* Ensemble sum of many whole images: for k = 0 .. n_img-1 in order,
+ * acc += (double) img_k, every image [acc_ns][acc_nf] of img_dtype.  The
+ * same bits as n_img calls of xrt_add_image in that order; one pass over the
+ * accumulator per 256 images instead of one per image.
+ *  host_dev_imgs  host array of n_img device pointers, read during the call.
+ * Enqueued on `stream`; images must not overlap the accumulator.
+ * Errors: EINVAL (NULL, dtype, sizes), ERANGE (n_img outside [0, 2^24]),
+ * EDEVICE. */
+xrt_status xrt_add_images(double *dev_acc, int32_t acc_nf, int32_t acc_ns,
+                          const void *const *host_dev_imgs, int32_t img_dtype, int64_t n_img,
+                          void *stream);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of independent shots on one device.
  *

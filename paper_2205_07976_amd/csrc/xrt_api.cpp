@@ -798,6 +798,30 @@ xrt_status xrt_add_image(double *dev_acc, int32_t acc_nf, int32_t acc_ns, const 
     return XRT_OK;
 }
 
+xrt_status xrt_add_images(double *dev_acc, int32_t acc_nf, int32_t acc_ns, const void *const *host_dev_imgs,
+                          int32_t img_dtype, int64_t n_img, void *stream)
+{
+    if (!dev_acc) return fail(XRT_EINVAL, "NULL accumulator");
+    if (img_dtype != XRT_F32 && img_dtype != XRT_F64) return fail(XRT_EINVAL, "unknown dtype %d", img_dtype);
+    if (acc_nf < 1 || acc_ns < 1) return fail(XRT_EINVAL, "accumulator sizes must be >= 1");
+    if ((int64_t)acc_nf * acc_ns >= ((int64_t)1 << 40)) return fail(XRT_ERANGE, "accumulator has 2^40 or more pixels");
+    if (n_img < 0 || n_img > ((int64_t)1 << 24)) return fail(XRT_ERANGE, "n_img must be in [0, 2^24]");
+    if (n_img == 0) return XRT_OK;
+    if (!host_dev_imgs) return fail(XRT_EINVAL, "NULL image list");
+    for (int64_t k = 0; k < n_img; ++k)
+        if (!host_dev_imgs[k]) return fail(XRT_EINVAL, "image %lld is NULL", (long long)k);
+    const int64_t n_pix = (int64_t)acc_nf * acc_ns;
+    for (int64_t k0 = 0; k0 < n_img; k0 += xrt::ADD_BATCH) {
+        xrt::AddBatch b;
+        std::memset(&b, 0, sizeof b);
+        const int n = (int)std::min<int64_t>(xrt::ADD_BATCH, n_img - k0);
+        for (int k = 0; k < n; ++k) b.img[k] = host_dev_imgs[k0 + k];
+        const hipError_t e = xrt::launch_add_images(dev_acc, n_pix, b, n, img_dtype == XRT_F64, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "xrt_add_images");
+    }
+    return XRT_OK;
+}
+
 xrt_status xrt_trace_terms(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal,
                            int64_t n, const int32_t *host_idx, double *host_S, double *host_h)
 {

@@ -178,6 +178,14 @@ hipError_t launch_exp(const double *x, int64_t n, double *y, hipStream_t stream)
 hipError_t launch_background(const BgParams &b, int precision, hipStream_t stream);
 hipError_t launch_add_image(double *acc, int64_t acc_nf, const void *img, int img_f64, int32_t nf, int32_t ns,
                             int32_t f0, int32_t s0, hipStream_t stream);
+// Up to ADD_BATCH whole-accumulator images added in order by one launch (the
+// image pointers travel in the kernel arguments).
+constexpr int ADD_BATCH = 256;
+struct AddBatch {
+    const void *img[ADD_BATCH];
+};
+hipError_t launch_add_images(double *acc, int64_t n_pix, const AddBatch &b, int n_img, int img_f64,
+                             hipStream_t stream);
 hipError_t launch_trace(const Params &p, int64_t n, const int32_t *idx, double *S, double *h,
                         hipStream_t stream);
 

@@ -1138,6 +1138,67 @@ hipError_t launch_add_image(double *acc, int64_t acc_nf, const void *img, int im
     return hipGetLastError();
 }
 
+// Many whole images into one accumulator: each lane takes a pixel, reads its
+// accumulator value once, adds the images' pixels in image order and writes
+// once, so the bits are those of one call per image in the same order while
+// the accumulator moves 16 bytes per pixel for the whole batch instead of per
+// image.
+__global__ __launch_bounds__(BLOCK) void add_images_kernel(double *acc, int64_t n_pix, const AddBatch b, int n_img,
+                                                           int img_f64)
+{
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n_pix; i += stride) {
+        double a = acc[i];
+        if (img_f64) {
+            for (int k = 0; k < n_img; ++k) a = a + ((const double *)b.img[k])[i];
+        } else {
+            for (int k = 0; k < n_img; ++k) a = a + (double)((const float *)b.img[k])[i];
+        }
+        acc[i] = a;
+    }
+}
+
+// The same with four pixels per lane and 16-byte accesses (every pointer
+// 16-byte aligned, binary32 images); the n_pix mod 4 last pixels one by one.
+__global__ __launch_bounds__(BLOCK) void add_images4_kernel(double *acc, int64_t n_pix, const AddBatch b, int n_img)
+{
+    const int64_t n4 = n_pix >> 2, stride = (int64_t)gridDim.x * BLOCK;
+    double2 *a2 = reinterpret_cast<double2 *>(acc);
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n4; i += stride) {
+        double2 a0 = a2[2 * i], a1 = a2[2 * i + 1];
+        for (int k = 0; k < n_img; ++k) {
+            const float4 f = reinterpret_cast<const float4 *>(b.img[k])[i];
+            a0.x = a0.x + (double)f.x;
+            a0.y = a0.y + (double)f.y;
+            a1.x = a1.x + (double)f.z;
+            a1.y = a1.y + (double)f.w;
+        }
+        a2[2 * i] = a0;
+        a2[2 * i + 1] = a1;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < (n_pix & 3)) {
+        const int64_t j = (n4 << 2) + threadIdx.x;
+        double a = acc[j];
+        for (int k = 0; k < n_img; ++k) a = a + (double)((const float *)b.img[k])[j];
+        acc[j] = a;
+    }
+}
+
+hipError_t launch_add_images(double *acc, int64_t n_pix, const AddBatch &b, int n_img, int img_f64,
+                             hipStream_t stream)
+{
+    bool aligned = ((uintptr_t)acc & 15) == 0;
+    for (int k = 0; k < n_img; ++k) aligned = aligned && ((uintptr_t)b.img[k] & 15) == 0;
+    if (!img_f64 && aligned) {
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(((n_pix >> 2) + BLOCK - 1) / BLOCK, 16384));
+        hipLaunchKernelGGL(add_images4_kernel, dim3(grid), dim3(BLOCK), 0, stream, acc, n_pix, b, n_img);
+        return hipGetLastError();
+    }
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_pix + BLOCK - 1) / BLOCK, 16384));
+    hipLaunchKernelGGL(add_images_kernel, dim3(grid), dim3(BLOCK), 0, stream, acc, n_pix, b, n_img, img_f64);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Padded F^2 tables: entry (a, b, c) of the (na+2P)(nb+2P)(nc+2P) box holds
 // F(a-P, b-P, c-P)^2 inside the tabulated range and F_default^2 elsewhere.

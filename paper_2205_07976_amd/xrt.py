@@ -105,7 +105,7 @@ SYMBOLS = ("xrt_version", "xrt_last_error", "xrt_fhkl_create", "xrt_fhkl_destroy
            "xrt_simulate", "xrt_simulate_rois", "xrt_backward_rois", "xrt_server_create",
            "xrt_server_destroy", "xrt_server_submit", "xrt_server_progress", "xrt_server_info",
            "xrt_server_image", "xrt_server_host_image", "xrt_server_release", "xrt_server_cancel", "xrt_cell_mats", "xrt_trace_terms", "xrt_sinpi", "xrt_exp",
-           "xrt_simulate_background", "xrt_add_image")
+           "xrt_simulate_background", "xrt_add_image", "xrt_add_images")
 XRT_SHOT_QUEUED, XRT_SHOT_RUNNING, XRT_SHOT_DONE = 0, 1, 2
 
 
@@ -133,6 +133,7 @@ def load():
                                             C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
     lib.xrt_add_image.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                   C.c_int32, C.c_int32, C.c_void_p]
+    lib.xrt_add_images.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p]
     lib.xrt_server_create.argtypes = [C.POINTER(ServerDesc), C.c_void_p, C.POINTER(C.c_void_p)]
     lib.xrt_server_destroy.argtypes = [C.c_void_p]
     lib.xrt_server_submit.argtypes = [C.c_void_p, C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal),
@@ -299,6 +300,26 @@ def add_image(acc, img, origin=(0, 0), stream=None):
     f0, s0 = (int(v) for v in origin)
     _check(load().xrt_add_image(C.c_void_p(acc.data_ptr()), acc.shape[1], acc.shape[0], C.c_void_p(img.data_ptr()),
                                 _dtype_code(img), img.shape[1], img.shape[0], f0, s0, _stream(stream)))
+    return acc
+
+
+def add_images(acc, imgs, stream=None):
+    """xrt_add_images: acc += img for every image of the list, in order, all
+    of acc's shape and one dtype (binary32 or binary64 GPU tensors).
+    Returns acc."""
+    import torch
+    if not (acc.is_cuda and acc.dtype == torch.float64 and acc.dim() == 2 and acc.is_contiguous()):
+        raise ValueError("acc must be a contiguous 2-D binary64 GPU tensor")
+    imgs = list(imgs)
+    if not imgs:
+        return acc
+    dt = imgs[0].dtype
+    for im in imgs:
+        if not (im.is_cuda and im.shape == acc.shape and im.dtype == dt and im.is_contiguous()):
+            raise ValueError("every image must be a contiguous GPU tensor of acc's shape and one dtype")
+    ptrs = (C.c_void_p * len(imgs))(*[im.data_ptr() for im in imgs])
+    _check(load().xrt_add_images(C.c_void_p(acc.data_ptr()), acc.shape[1], acc.shape[0], ptrs, _dtype_code(imgs[0]),
+                                 len(imgs), _stream(stream)))
     return acc
 
 

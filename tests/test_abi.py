@@ -169,6 +169,20 @@ def test_add_image_validation():
         assert err()
 
 
+def test_add_images_validation():
+    lib = xrt.load()
+    ptrs = (C.c_void_p * 2)(8, 16)
+    bad = (C.c_void_p * 2)(8, None)
+    assert lib.xrt_add_images(None, 4, 4, ptrs, 0, 2, None) == xrt.XRT_EINVAL
+    assert lib.xrt_add_images(C.c_void_p(8), 4, 4, ptrs, 3, 2, None) == xrt.XRT_EINVAL
+    assert lib.xrt_add_images(C.c_void_p(8), 0, 4, ptrs, 0, 2, None) == xrt.XRT_EINVAL
+    assert lib.xrt_add_images(C.c_void_p(8), 4, 4, ptrs, 0, -1, None) == xrt.XRT_ERANGE
+    assert lib.xrt_add_images(C.c_void_p(8), 4, 4, None, 0, 2, None) == xrt.XRT_EINVAL
+    assert lib.xrt_add_images(C.c_void_p(8), 4, 4, bad, 0, 2, None) == xrt.XRT_EINVAL
+    assert "image 1" in err()
+    assert lib.xrt_add_images(C.c_void_p(8), 4, 4, None, 0, 0, None) == xrt.XRT_OK  # nothing to add
+
+
 def test_fhkl_create_validation():
     lib = xrt.load()
     h = C.c_void_p()

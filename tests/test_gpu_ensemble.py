@@ -58,6 +58,32 @@ def test_ensemble_sum_in_order():
     assert np.array_equal(acc.cpu().numpy(), ens.ensemble_sum(shape, imgs, origins))
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("n", [1, 7, 300])
+def test_add_images_in_one_pass(dtype, n):
+    """n whole images in one call (300: two launches of up to 256) give the
+    bits of n single-image calls in the same order and of the definition."""
+    rng = np.random.default_rng(n)
+    shape = (37, 53)
+    acc0 = rng.standard_normal(shape)
+    imgs = [(rng.standard_normal(shape) * 10.0 ** rng.integers(-3, 4)).astype(dtype) for _ in range(n)]
+    timgs = [torch.as_tensor(im, device="cuda") for im in imgs]
+    batch = torch.as_tensor(acc0, device="cuda")
+    xrt.add_images(batch, timgs)
+    one = torch.as_tensor(acc0, device="cuda")
+    for im in timgs:
+        xrt.add_image(one, im)
+    torch.cuda.synchronize()
+    assert torch.equal(batch, one)
+    ref = acc0
+    for im in imgs[:40]:  # the definition on the first 40 (the oracle's loops are slow)
+        ref = ens.add_image(ref, im, 0, 0)
+    part = torch.as_tensor(acc0, device="cuda")
+    xrt.add_images(part, timgs[:40])
+    torch.cuda.synchronize()
+    assert np.array_equal(part.cpu().numpy(), ref)
+
+
 def _small_served_shots(n, seed):
     """Served-stream shots (random orientation, 1-100 sources, 1-200 domains,
     N in [5, 40]) with their regions cut to at most 96 x 96 pixels."""
