@@ -255,23 +255,54 @@ __device__ __forceinline__ Pixel tile_pixel(const Params &p, int tile)
     return px;
 }
 
-// Fractional Miller indices of term r.  Without PF the matrix is read where
-// it is used (scalar loads for the standalone kernel); with PF, m holds
-// matrix r and is replaced by matrix r + 1, whose reads are issued before h.
-template <bool PF>
-__device__ __forceinline__ void hkl(const Params &p, const double *mats, double m[9], int r, const double S[3],
-                                    double h[3])
+// The spindle x domain sum of one (sample point, source), terms in the order
+// r = 0, 1, ..., n_rot - 1: a plain binary64 sum, or a Kahan-compensated
+// binary32 one in the mixed form.
+template <int PREC, int SHAPE, bool CLAMP>
+struct RotSum {
+    double s64 = 0.0;
+    float s = 0.0f, c = 0.0f;
+    __device__ __forceinline__ void add(const Params &p, __amdgpu_buffer_rsrc_t tab, const double M[9],
+                                        const double S[3])
+    {
+        double h[3];
+        miller(M, S, h);
+        if (PREC == XRT_FP64)
+            s64 += term_f64<SHAPE, CLAMP>(p, tab, h);
+        else
+            kahn_add(s, c, term_mixed<SHAPE, CLAMP>(p, tab, h));
+    }
+};
+
+__device__ __forceinline__ void load9(double m[9], const double *src)
 {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) m[q] = src[q];
+}
+
+// Without PF the matrix of term r is read where it is used (scalar loads in
+// the standalone kernel).  With PF (tables in LDS) two register sets take
+// turns: the reads of matrix r + 1 are issued before term r is evaluated, and
+// the loop is unrolled by two so that no register copies are needed between
+// terms.
+template <int PREC, int SHAPE, bool CLAMP, bool PF>
+__device__ __forceinline__ void rot_sum(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *mats,
+                                        const double S[3], RotSum<PREC, SHAPE, CLAMP> &acc)
+{
+    const int n = p.n_rot;
     if (PF) {
-        double mn[9];
-        const double *nx = mats + 9 * (r + 1 < p.n_rot ? r + 1 : r);
-#pragma unroll
-        for (int q = 0; q < 9; ++q) mn[q] = nx[q];
-        miller(m, S, h);
-#pragma unroll
-        for (int q = 0; q < 9; ++q) m[q] = mn[q];
+        double ma[9], mb[9];
+        load9(ma, mats);
+        int r = 0;
+        for (; r + 1 < n; r += 2) {
+            load9(mb, mats + 9 * (r + 1));
+            acc.add(p, tab, ma, S);
+            load9(ma, mats + 9 * (r + 2 < n ? r + 2 : r + 1));
+            acc.add(p, tab, mb, S);
+        }
+        if (r < n) acc.add(p, tab, ma, S);
     } else {
-        miller(mats + 9 * r, S, h);
+        for (int r = 0; r < n; ++r) acc.add(p, tab, mats + 9 * r, S);
     }
 }
 
@@ -303,28 +334,12 @@ __device__ __forceinline__ double pixel_sum(const Params &p, __amdgpu_buffer_rsr
             double S[3];
             scatter(src, d, S);
             const double w = src[SRC_WEIGHT] * polarization(src, d, p.kahn) * wgeo;
-            double m[9];  // PF: the matrix of the current term
-            if (PF) {
-#pragma unroll
-                for (int c = 0; c < 9; ++c) m[c] = mats[c];
-            }
-            if (PREC == XRT_FP64) {
-                double sub = 0.0;
-                for (int r = 0; r < p.n_rot; ++r) {
-                    double h[3];
-                    hkl<PF>(p, mats, m, r, S, h);
-                    sub += term_f64<SHAPE, CLAMP>(p, tab, h);
-                }
-                acc64 = __builtin_fma(w, sub, acc64);
-            } else {
-                float s = 0.0f, c = 0.0f;
-                for (int r = 0; r < p.n_rot; ++r) {
-                    double h[3];
-                    hkl<PF>(p, mats, m, r, S, h);
-                    kahn_add(s, c, term_mixed<SHAPE, CLAMP>(p, tab, h));
-                }
-                kahn_add(acc, accc, (float)w * (s - c));
-            }
+            RotSum<PREC, SHAPE, CLAMP> rs;
+            rot_sum<PREC, SHAPE, CLAMP, PF>(p, tab, mats, S, rs);
+            if (PREC == XRT_FP64)
+                acc64 = __builtin_fma(w, rs.s64, acc64);
+            else
+                kahn_add(acc, accc, (float)w * (rs.s - rs.c));
         }
         q += j1 - j0;
         j0 = 0;
