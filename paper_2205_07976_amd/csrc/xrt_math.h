@@ -35,13 +35,26 @@ __device__ __forceinline__ float sinpi_over_x(float y)
     return p;
 }
 
+// a * b + c, rounded once, as the three-address v_fma_f64 with c held in
+// scalar registers.  For a Horner step with a constant coefficient c the
+// compiler otherwise emits the two-address v_fmac_f64, whose accumulator is
+// c, after copying c from the vector registers that hold it across the loop:
+// one 64-bit move per step.  The value is the same either way (one rounding).
+__device__ __forceinline__ double fma_sc(double a, double b, double c)
+{
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+    return d;
+}
+
 // exp(e) in binary64 for the Gaussian lattice factor: e = n ln2 + r with
 // n = rint(e / ln2) and r reduced by two fused multiply-adds against ln2 split
 // into a binary64 head and tail (Cody and Waite's reduction); exp(r) on
 // |r| <= ln2/2 is a degree-11 relative-minimax polynomial (fit_exp.py in this
 // directory: 2.3e-17 with the coefficients as stored), evaluated by Horner's
 // rule with fused multiply-adds; 2^n is applied by ldexp, which also yields
-// the subnormal results and 0 below the binary64 range.  For e <= 709 (the
+// the subnormal results and 0 below the binary64 range.  The Horner steps
+// with coefficients other than 1 use fma_sc.  For e <= 709 (the
 // lattice exponents are at most log(Na^2 Nb^2 Nc^2)); e is raised to -1100
 // first, where the result is 0 either way, so n fits an int.
 __device__ __forceinline__ double exp_f64(double e)
@@ -51,15 +64,15 @@ __device__ __forceinline__ double exp_f64(double e)
     double r = __builtin_fma(-n, 0.6931471805599453, e);
     r = __builtin_fma(-n, 2.3190468138462996e-17, r);
     double p = 2.4994304884817207e-08;
-    p = __builtin_fma(p, r, 2.7632293279459877e-07);
-    p = __builtin_fma(p, r, 2.7557622530872255e-06);
-    p = __builtin_fma(p, r, 2.4801486521427463e-05);
-    p = __builtin_fma(p, r, 0.00019841269432679237);
-    p = __builtin_fma(p, r, 0.0013888888951223987);
-    p = __builtin_fma(p, r, 0.00833333333355927);
-    p = __builtin_fma(p, r, 0.04166666666649277);
-    p = __builtin_fma(p, r, 0.1666666666666617);
-    p = __builtin_fma(p, r, 0.5000000000000018);
+    p = fma_sc(p, r, 2.7632293279459877e-07);
+    p = fma_sc(p, r, 2.7557622530872255e-06);
+    p = fma_sc(p, r, 2.4801486521427463e-05);
+    p = fma_sc(p, r, 0.00019841269432679237);
+    p = fma_sc(p, r, 0.0013888888951223987);
+    p = fma_sc(p, r, 0.00833333333355927);
+    p = fma_sc(p, r, 0.04166666666649277);
+    p = fma_sc(p, r, 0.1666666666666617);
+    p = fma_sc(p, r, 0.5000000000000018);
     p = __builtin_fma(p, r, 1.0);
     p = __builtin_fma(p, r, 1.0);
     return __builtin_ldexp(p, (int)n);
