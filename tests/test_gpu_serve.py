@@ -75,6 +75,28 @@ def test_served_equal_standalone_in_mix_and_alone(precision):
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_served_short_rotation_lists(precision):
+    """The served kernel reads the spindle x domain matrices two at a time
+    (the loop unrolled by two, the next matrix read during the current
+    term): lists of 1, 2, 3 and 4 matrices, from domains alone and from
+    spindle steps x domains, give the standalone images bit for bit."""
+    base, shots = small_served_shots(8, seed=45, max_side=40)
+    cases = [(1, 1), (2, 1), (3, 1), (4, 1), (1, 2), (3, 2), (2, 2), (1, 3)]  # (domains, spindle steps)
+    shots = [s.replace(umats=s.umats[:1].repeat(m, axis=0) if len(s.umats) < m else s.umats[:m].copy(),
+                       n_phi=k, phi0=0.01, dphi=0.02) for s, (m, k) in zip(shots, cases)]
+    assert sorted(len(s.umats) * s.n_phi for s in shots) == [1, 2, 2, 3, 3, 4, 4, 6]
+    fh = xrt.Fhkl.from_shot(base)
+    ref = [xrt.simulate(s, fh, precision=precision).cpu().numpy() for s in shots]
+    srv = xrt.Server(fh, hbm_budget=64 << 20, precision=precision)
+    tickets = [srv.submit(s) for s in shots]
+    drain(srv, tickets)
+    for i, t in enumerate(tickets):
+        assert np.array_equal(srv.image(t).cpu().numpy(), ref[i]), f"rotation list {cases[i]} differs"
+        srv.release(t)
+    srv.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_served_gaussian_shape(precision):
     """A server of the Gaussian shape (real N, the refinement crystal's
     lattice form): every image equals the standalone Gaussian kernel's bit
