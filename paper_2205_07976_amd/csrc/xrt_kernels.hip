@@ -436,8 +436,10 @@ hipError_t launch_spots(const Params &p, int precision, bool clamp, hipStream_t 
 // w P F^2; no spindle or mosaic loop and no table gather, so it is a short
 // VALU-bound kernel with the spots kernel's pixel layout (one pixel per lane,
 // a 16 x 16 tile per workgroup).  The curve is staged in LDS as one record
-// per interval.  The source loop is unrolled by two, so the scalar loads of
-// the next source row overlap the current term.
+// per interval.  The binary64 source loop reads the next source row while it
+// evaluates the current one, so those loads overlap the term; the binary32
+// loop, whose terms are shorter, is unrolled by two instead (either form
+// loses 6-20 % in the other precision).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -487,14 +489,36 @@ __device__ __forceinline__ R bg_curve(const BgKnot<R> *kt, BgKnot<R> &c, int &k,
     return fma_r(s - c.x, c.m, c.y);
 }
 
-// Kahn factor of one source row (binary64 or binary32 copy), P =
-// (1 + c^2 - K (x^2 - y^2)) / 2 as in the spots kernel, by fused products.
+// The fields of one source row that a background term reads (binary64, or
+// the binary32 copy with its direction tails lo), held in registers so that
+// the source loop can read row j + 1 while it evaluates row j.
 template <typename R>
-__device__ __forceinline__ R bg_polarization(const R *src, const R d[3], R K)
+struct BgRow {
+    R dir[3], lo[3], e[3], b[3], hil, w;
+};
+
+template <typename R>
+__device__ __forceinline__ void bg_row(BgRow<R> &r, const R *src, bool tails)
 {
-    const R c = fma_r(d[2], src[SRC_DIR + 2], fma_r(d[1], src[SRC_DIR + 1], d[0] * src[SRC_DIR]));
-    const R x = fma_r(d[2], src[SRC_E + 2], fma_r(d[1], src[SRC_E + 1], d[0] * src[SRC_E]));
-    const R y = fma_r(d[2], src[SRC_B + 2], fma_r(d[1], src[SRC_B + 1], d[0] * src[SRC_B]));
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        r.dir[i] = src[SRC_DIR + i];
+        r.lo[i] = tails ? src[SRC32_DIR_LO + i] : R(0);
+        r.e[i] = src[SRC_E + i];
+        r.b[i] = src[SRC_B + i];
+    }
+    r.hil = src[SRC_HIL];
+    r.w = src[SRC_WEIGHT];
+}
+
+// Kahn factor of one source row, P = (1 + c^2 - K (x^2 - y^2)) / 2 as in the
+// spots kernel, by fused products.
+template <typename R>
+__device__ __forceinline__ R bg_polarization(const BgRow<R> &s, const R d[3], R K)
+{
+    const R c = fma_r(d[2], s.dir[2], fma_r(d[1], s.dir[1], d[0] * s.dir[0]));
+    const R x = fma_r(d[2], s.e[2], fma_r(d[1], s.e[1], d[0] * s.e[0]));
+    const R y = fma_r(d[2], s.b[2], fma_r(d[1], s.b[1], d[0] * s.b[0]));
     return R(0.5) * fma_r(-K, fma_r(x, x, -(y * y)), fma_r(c, c, R(1)));
 }
 
@@ -524,15 +548,16 @@ __device__ __forceinline__ double bg_pixel_sum(const Params &p, const BgKnot<BgR
                 const double wgeo = sample_weight(p, d, dist, t);
                 if constexpr (PREC == XRT_FP64) {
                     double sub = 0.0;
-#pragma unroll 2
+                    BgRow<double> cur, nxt;
+                    bg_row(cur, srcs, false);
                     for (int j = 0; j < p.n_src; ++j) {
-                        const double *src = srcs + SRC_STRIDE * j;
-                        const double e0 = d[0] - src[SRC_DIR], e1 = d[1] - src[SRC_DIR + 1],
-                                     e2 = d[2] - src[SRC_DIR + 2];
+                        bg_row(nxt, srcs + SRC_STRIDE * (j + 1 < p.n_src ? j + 1 : j), false);
+                        const double e0 = d[0] - cur.dir[0], e1 = d[1] - cur.dir[1], e2 = d[2] - cur.dir[2];
                         const double len = root_small(__builtin_fma(e2, e2, __builtin_fma(e1, e1, e0 * e0)));
-                        const double F = bg_curve(kt, ck, k, x0, len * src[SRC_HIL]);
-                        const double P = bg_polarization(src, d, p.kahn);
-                        sub = __builtin_fma(src[SRC_WEIGHT] * P, F * F, sub);
+                        const double F = bg_curve(kt, ck, k, x0, len * cur.hil);
+                        const double P = bg_polarization(cur, d, p.kahn);
+                        sub = __builtin_fma(cur.w * P, F * F, sub);
+                        cur = nxt;
                     }
                     acc64 = __builtin_fma(wgeo, sub, acc64);
                 } else {
@@ -546,14 +571,15 @@ __device__ __forceinline__ double bg_pixel_sum(const Params &p, const BgKnot<BgR
                     float s = 0.0f, c = 0.0f;
 #pragma unroll 2
                     for (int j = 0; j < p.n_src; ++j) {
-                        const float *src32 = srcs32 + SRC32_STRIDE * j;
-                        const float e0 = (d32[0] - src32[SRC_DIR]) + (dlo[0] - src32[SRC32_DIR_LO]);
-                        const float e1 = (d32[1] - src32[SRC_DIR + 1]) + (dlo[1] - src32[SRC32_DIR_LO + 1]);
-                        const float e2 = (d32[2] - src32[SRC_DIR + 2]) + (dlo[2] - src32[SRC32_DIR_LO + 2]);
+                        BgRow<float> cur;
+                        bg_row(cur, srcs32 + SRC32_STRIDE * j, true);
+                        const float e0 = (d32[0] - cur.dir[0]) + (dlo[0] - cur.lo[0]);
+                        const float e1 = (d32[1] - cur.dir[1]) + (dlo[1] - cur.lo[1]);
+                        const float e2 = (d32[2] - cur.dir[2]) + (dlo[2] - cur.lo[2]);
                         const float len = root_small(__builtin_fmaf(e2, e2, __builtin_fmaf(e1, e1, e0 * e0)));
-                        const float F = bg_curve(kt, ck, k, x0, len * src32[SRC_HIL]);
-                        const float P = bg_polarization(src32, d32, (float)p.kahn);
-                        kahn_add(s, c, src32[SRC_WEIGHT] * P * (F * F));
+                        const float F = bg_curve(kt, ck, k, x0, len * cur.hil);
+                        const float P = bg_polarization(cur, d32, (float)p.kahn);
+                        kahn_add(s, c, cur.w * P * (F * F));
                     }
                     kahn_add(acc, accc, (float)wgeo * (s - c));
                 }
