@@ -712,7 +712,7 @@ __device__ __forceinline__ long long serve_claim(const ServeArgs &a)
 }
 
 template <int PREC, int SHAPE>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void serve_kernel(const ServeArgs a)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PREC == XRT_MIXED ? 4 : 3))) void serve_kernel(const ServeArgs a)
 {
     __shared__ ShotDesc sd;
     __shared__ double smats[9 * SERVE_MAX_ROT];
