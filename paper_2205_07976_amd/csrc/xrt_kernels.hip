@@ -588,7 +588,7 @@ __device__ __forceinline__ double bg_pixel_sum(const Params &p, const BgKnot<BgR
 }
 
 template <int PREC>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void background_kernel(const BgParams b)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void background_kernel(const BgParams b)
 {
     using R = BgReal<PREC>;
     extern __shared__ double bg_lds[];
