@@ -400,7 +400,10 @@ xrt_status xrt_server_host_image(xrt_server *srv, uint64_t ticket, const void **
 
 /* Free a finished shot's memory and slot (write-out: its host memory; the
  * device memory and the slot were freed when the copy completed).  EBUSY if
- * not done. */
+ * not done.  The caller must have completed every read of the image first
+ * (a copy enqueued on another stream included: synchronise it): the freed
+ * region goes to the next admitted shot, whose pixels the running persistent
+ * kernel may write at once. */
 xrt_status xrt_server_release(xrt_server *srv, uint64_t ticket);
 
 /* Withdraw a shot that is still queued (not yet admitted): the ticket is

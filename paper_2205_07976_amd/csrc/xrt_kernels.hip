@@ -180,41 +180,69 @@ __device__ __forceinline__ double term_f64(const Params &p, __amdgpu_buffer_rsrc
     return load_f64(tab, table_offset<CLAMP>(p, hr, p.sa8, p.sb8, 8.0, p.off8)) * L2;
 }
 
-// One term, mixed: h, f and g in binary64 (they decide the conditioning),
-// everything after the reduced arguments in binary32.
-template <int SHAPE, bool CLAMP>
-__device__ __forceinline__ float term_mixed(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3])
+// One sincg term, mixed: h, f and g in binary64 (they decide the
+// conditioning), everything after the reduced arguments in binary32.
+template <bool CLAMP>
+__device__ __forceinline__ float term_mixed_sincg(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3])
 {
     double hr[3];
-    float L2;
-    if (SHAPE == XRT_SHAPE_SINCG) {
-        float num = 1.0f, den = 1.0f;
+    float num = 1.0f, den = 1.0f;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            hr[i] = __builtin_rint(h[i]);
-            const double fa = __builtin_fmax(__builtin_fabs(h[i] - hr[i]), F_FLOOR);
-            const double t = p.N[i] * fa;
-            const float g = (float)(t - __builtin_rint(t));
-            const float f = (float)fa;
-            num *= sinpi_reduced(g);
-            den *= sinpi_reduced(f);
-        }
-        const float q = num * __builtin_amdgcn_rcpf(den);
-        L2 = q * q;
-    } else {
-        double e = 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            hr[i] = __builtin_rint(h[i]);
-            const double f = h[i] - hr[i];
-            e = __builtin_fma(-p.gk[i], f * f, e);
-        }
-        L2 = __expf((float)(e + p.ln_n2));
+    for (int i = 0; i < 3; ++i) {
+        hr[i] = __builtin_rint(h[i]);
+        const double fa = __builtin_fmax(__builtin_fabs(h[i] - hr[i]), F_FLOOR);
+        const double t = p.N[i] * fa;
+        const float g = (float)(t - __builtin_rint(t));
+        const float f = (float)fa;
+        num *= sinpi_reduced(g);
+        den *= sinpi_reduced(f);
     }
-    return load_f32(tab, table_offset<CLAMP>(p, hr, p.sa4, p.sb4, 4.0, p.off4)) * L2;
+    const float q = num * __builtin_amdgcn_rcpf(den);
+    return load_f32(tab, table_offset<CLAMP>(p, hr, p.sa4, p.sb4, 4.0, p.off4)) * (q * q);
 }
 
-__device__ __forceinline__ void kahn_add(float &s, float &c, float x)
+// The Gaussian lattice exponent e = ln(Na^2 Nb^2 Nc^2) - sum_i gk_i f_i^2 of
+// h, in binary64 (the same sequence as the binary64 term), with the rounded
+// indices hr and the reduced arguments f.
+__device__ __forceinline__ double gauss_exponent(const Params &p, const double h[3], double hr[3], double f[3])
+{
+    double e = p.ln_n2;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        hr[i] = __builtin_rint(h[i]);
+        f[i] = h[i] - hr[i];
+        e = __builtin_fma(-p.gk[i], f[i] * f[i], e);
+    }
+    return e;
+}
+
+// Mixed Gaussian sums: the exponents of the terms of one (sample point,
+// source) span hundreds of e-folds (down to about -950 at N = 20 far from a
+// spot), beyond the binary32 range and beyond what a binary32 exponent
+// resolves (its rounding at |e| = 500 alone is a relative 3e-5).  The sum
+// therefore keeps a reference exponent m in binary64 and adds the binary32
+// terms F^2 exp(e - m): m is the exponent of the first term with a nonzero
+// F^2 and is raised to a later such term's exponent when that exceeds it by
+// more than GAUSS_REF_STEP, the sum so far being rescaled by exp(m_old - m).
+// So the rounded (float)(e - m) of every term that matters is below the
+// step in magnitude (an error of at most 2^-21 in the exponent), no term
+// exceeds F^2 e^8, and a term is lost to the binary32 range only when it is
+// more than e^87 below the reference.  Terms with F^2 = 0 never move m (their
+// exponent is clamped to the step, so 0 * exp stays 0).  The value of the
+// sum is exp(m) (s - c), formed in binary64 by the binary64 term's exp.
+constexpr float GAUSS_REF_STEP = 8.0f;
+
+__device__ __forceinline__ float gauss_rescale(double &m, double e, float F2)
+{
+    float k = 1.0f;
+    if (F2 > 0.0f && e > m + (double)GAUSS_REF_STEP) {
+        k = __expf((float)(m - e));  // 0 for the first such term (m = -inf)
+        m = e;
+    }
+    return k;
+}
+
+__device__ __forceinline__ void kahan_add(float &s, float &c, float x)
 {
     const float y = x - c;
     const float t = s + y;
@@ -262,15 +290,35 @@ template <int PREC, int SHAPE, bool CLAMP>
 struct RotSum {
     double s64 = 0.0;
     float s = 0.0f, c = 0.0f;
+    double m = -__builtin_inf();  // mixed Gaussian: reference exponent
     __device__ __forceinline__ void add(const Params &p, __amdgpu_buffer_rsrc_t tab, const double M[9],
                                         const double S[3])
     {
         double h[3];
         miller(M, S, h);
-        if (PREC == XRT_FP64)
+        if constexpr (PREC == XRT_FP64) {
             s64 += term_f64<SHAPE, CLAMP>(p, tab, h);
+        } else if constexpr (SHAPE == XRT_SHAPE_SINCG) {
+            kahan_add(s, c, term_mixed_sincg<CLAMP>(p, tab, h));
+        } else {
+            double hr[3], f[3];
+            const double e = gauss_exponent(p, h, hr, f);
+            const float F2 = load_f32(tab, table_offset<CLAMP>(p, hr, p.sa4, p.sb4, 4.0, p.off4));
+            const float k = gauss_rescale(m, e, F2);
+            s *= k;
+            c *= k;
+            kahan_add(s, c, F2 * __expf(__builtin_fminf((float)(e - m), GAUSS_REF_STEP)));
+        }
+    }
+    // The sum in binary64 (mixed Gaussian: exp(m) (s - c)).
+    __device__ __forceinline__ double value() const
+    {
+        if constexpr (PREC == XRT_FP64)
+            return s64;
+        else if constexpr (SHAPE == XRT_SHAPE_SINCG)
+            return (double)(s - c);
         else
-            kahn_add(s, c, term_mixed<SHAPE, CLAMP>(p, tab, h));
+            return exp_f64(m) * (double)(s - c);
     }
 };
 
@@ -336,15 +384,17 @@ __device__ __forceinline__ double pixel_sum(const Params &p, __amdgpu_buffer_rsr
             const double w = src[SRC_WEIGHT] * polarization(src, d, p.kahn) * wgeo;
             RotSum<PREC, SHAPE, CLAMP> rs;
             rot_sum<PREC, SHAPE, CLAMP, PF>(p, tab, mats, S, rs);
-            if (PREC == XRT_FP64)
-                acc64 = __builtin_fma(w, rs.s64, acc64);
+            // binary64 outer sum, except for mixed sincg (Kahan binary32):
+            // the mixed Gaussian sums leave the binary32 range
+            if constexpr (PREC == XRT_MIXED && SHAPE == XRT_SHAPE_SINCG)
+                kahan_add(acc, accc, (float)w * (rs.s - rs.c));
             else
-                kahn_add(acc, accc, (float)w * (rs.s - rs.c));
+                acc64 = __builtin_fma(w, rs.value(), acc64);
         }
         q += j1 - j0;
         j0 = 0;
     }
-    return PREC == XRT_FP64 ? acc64 : (double)(acc - accc);
+    return PREC == XRT_MIXED && SHAPE == XRT_SHAPE_SINCG ? (double)(acc - accc) : acc64;
 }
 
 // Part k of K of the outer iterations: [k n / K, (k + 1) n / K).
@@ -579,9 +629,9 @@ __device__ __forceinline__ double bg_pixel_sum(const Params &p, const BgKnot<BgR
                         const float len = root_small(__builtin_fmaf(e2, e2, __builtin_fmaf(e1, e1, e0 * e0)));
                         const float F = bg_curve(kt, ck, k, x0, len * cur.hil);
                         const float P = bg_polarization(cur, d32, (float)p.kahn);
-                        kahn_add(s, c, cur.w * P * (F * F));
+                        kahan_add(s, c, cur.w * P * (F * F));
                     }
-                    kahn_add(acc, accc, (float)wgeo * (s - c));
+                    kahan_add(acc, accc, (float)wgeo * (s - c));
                 }
             }
     return PREC == XRT_FP64 ? acc64 : (double)(acc - accc);
@@ -981,29 +1031,36 @@ __device__ __forceinline__ void grad_term_f64(const Params &p, __amdgpu_buffer_r
     acc[12] += base;
 }
 
-// Mixed: Q^T S, h and f in binary64; the exponent, the lattice factor and the
-// products in binary32 (partial sums over the domain loop in binary32, then
-// binary64).
+// Mixed: Q^T S, h, f and the exponent in binary64; the lattice factor, the
+// derivatives and the products in binary32, as terms F^2 exp(e - m) against
+// the reference exponent m of the forward's mixed Gaussian sums (the 13
+// binary32 sums of one (sample point, source) are rescaled with m and added
+// into binary64 as exp(m) times their value).
 template <bool CLAMP>
 __device__ __forceinline__ void grad_term_mixed(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *Q,
-                                                const double S[3], float w, float acc[13])
+                                                const double S[3], float w, float acc[13], double &m)
 {
-    double Sp[3], hr[3];
+    double Sp[3], hr[3], fd[3];
     float f[3], Sf[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         Sp[c] = __builtin_fma(Q[6 + c], S[2], __builtin_fma(Q[3 + c], S[1], Q[c] * S[0]));
         Sf[c] = (float)Sp[c];
     }
-    float e = (float)p.ln_n2;
+    double h[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const double h = __builtin_fma(p.m0[3 * i + 2], Sp[2], __builtin_fma(p.m0[3 * i + 1], Sp[1], p.m0[3 * i] * Sp[0]));
-        hr[i] = __builtin_rint(h);
-        f[i] = (float)(h - hr[i]);
-        e = __builtin_fmaf(-(float)p.gk[i], f[i] * f[i], e);
+    for (int i = 0; i < 3; ++i)
+        h[i] = __builtin_fma(p.m0[3 * i + 2], Sp[2], __builtin_fma(p.m0[3 * i + 1], Sp[1], p.m0[3 * i] * Sp[0]));
+    const double e = gauss_exponent(p, h, hr, fd);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) f[i] = (float)fd[i];
+    const float F2 = load_f32(tab, table_offset<CLAMP>(p, hr, p.sa4, p.sb4, 4.0, p.off4));
+    const float k = gauss_rescale(m, e, F2);
+    if (k != 1.0f) {
+#pragma unroll
+        for (int c = 0; c < 13; ++c) acc[c] *= k;
     }
-    const float base = w * load_f32(tab, table_offset<CLAMP>(p, hr, p.sa4, p.sb4, 4.0, p.off4)) * __expf(e);
+    const float base = w * F2 * __expf(__builtin_fminf((float)(e - m), GAUSS_REF_STEP));
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const float dh = base * (float)p.m2gk[i] * f[i];
@@ -1058,10 +1115,12 @@ __global__ __launch_bounds__(BLOCK) void grad_kernel(const Params p, const void 
                         float a32[13];
 #pragma unroll
                         for (int c = 0; c < 13; ++c) a32[c] = 0.0f;
+                        double m = -__builtin_inf();
                         for (int r = 0; r < p.n_rot; ++r)
-                            grad_term_mixed<CLAMP>(p, tab, p.qmats + 9 * r, S, (float)w, a32);
+                            grad_term_mixed<CLAMP>(p, tab, p.qmats + 9 * r, S, (float)w, a32, m);
+                        const double em = exp_f64(m);
 #pragma unroll
-                        for (int c = 0; c < 13; ++c) acc[c] += (double)a32[c];
+                        for (int c = 0; c < 13; ++c) acc[c] = __builtin_fma(em, (double)a32[c], acc[c]);
                     }
                 }
             }

@@ -108,7 +108,7 @@ class Scheduler {
     // ring of chunk records.
     Scheduler(uint64_t dev_bytes, uint64_t host_bytes, int max_resident, int n_wg, uint32_t ring)
         : dev_(dev_bytes), host_(host_bytes), max_resident_(max_resident), n_wg_(std::max(n_wg, 1)),
-          depth_(std::min<size_t>(ring - 1, 2 * (size_t)std::max(n_wg, 1)))
+          depth_(std::min<size_t>(ring - 1, 2 * (size_t)std::max(n_wg, 1))), ring_(ring)
     {
     }
 
@@ -154,17 +154,22 @@ class Scheduler {
         return 0;
     }
 
-    // Publication while fewer than `depth` chunks are in flight: the next
-    // chunk always comes from the admitted shot with the least work published
-    // so far (pixel-terms; ties to the earlier ticket), so resident shots
-    // share the device evenly by work whatever their chunk sizes, and a shot
-    // admitted later joins at the current level.  emit(const Chunk &, Work &)
-    // writes the record.  Returns the number of chunks published.
+    // Publication while fewer than `depth` chunks are in flight and the new
+    // sequence number stays within `ring` of the oldest chunk still in flight
+    // (records and done flags live at seq % ring: a slow chunk must not share
+    // its slot with a later one): the next chunk always comes from the
+    // admitted shot with the least work published so far (pixel-terms; ties
+    // to the earlier ticket), so resident shots share the device evenly by
+    // work whatever their chunk sizes, and a shot admitted later joins at the
+    // current level.  emit(const Chunk &, Work &) writes the record.  Returns
+    // the number of chunks published.
     template <class Emit>
     size_t publish(Emit emit)
     {
         size_t n = 0;
-        while (inflight_.size() < depth_ && !admitted_.empty()) {
+        // inflight_ is in publication order: its front is the oldest chunk
+        while (inflight_.size() < depth_ && !admitted_.empty() &&
+               (inflight_.empty() || tail_ - inflight_.front().seq < ring_)) {
             size_t best = 0;
             for (size_t i = 1; i < admitted_.size(); ++i) {
                 const Work &a = work_[admitted_[i]], &b = work_[admitted_[best]];
@@ -294,6 +299,7 @@ class Scheduler {
     int max_resident_;
     int n_wg_;
     size_t depth_;
+    uint64_t ring_;
     uint64_t resident_ = 0, tail_ = 0;
     double vtime_ = 0;  // published work of the shot served last
     std::deque<uint64_t> queue_;         // submitted, not admitted (FIFO)

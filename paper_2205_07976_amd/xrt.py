@@ -461,7 +461,9 @@ class Server:
 
     def image(self, ticket, copy=True):
         """The finished image as a [roi_ns, roi_nf] GPU tensor: a view of the
-        arena (valid until release) or, by default, a copy of it."""
+        arena (valid until release; every read of it must have completed
+        before release, since the freed region goes to the next admitted shot)
+        or, by default, a copy of it that is complete when this returns."""
         import torch
         info = self.info(ticket)
         p = C.c_void_p()
@@ -473,7 +475,15 @@ class Server:
                                         "data": (p.value, False), "version": 2, "strides": None}
 
         view = torch.as_tensor(_View(), device="cuda")
-        return view.clone() if copy else view
+        if not copy:
+            return view
+        out = view.clone()
+        # the clone runs on torch's current stream, not the server's: wait for
+        # it, so that a release right after this call cannot hand the region
+        # to a shot whose pixels the persistent kernel writes before the copy
+        # has read them
+        torch.cuda.current_stream().synchronize()
+        return out
 
     def host_image(self, ticket):
         """Write-out servers: the finished image in the server's pinned host

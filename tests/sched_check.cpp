@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <algorithm>
 #include <map>
 #include <random>
 #include <set>
@@ -314,6 +315,55 @@ static void check_ring_sequence()
     CHECK(d.log.size() > 16 * 10);
 }
 
+static void check_ring_slot_reuse()
+{
+    printf("ring: a slow chunk held while many short ones finish never shares its slot\n");
+    const uint32_t ring = 16;
+    Scheduler s(1 << 30, 1 << 22, 4, 2, ring);  // depth min(15, 4)
+    Device d(s);
+    s.submit(shot(1, 4096, 20000, 10));
+    s.admit([](Work &) { return 0; });
+    d.publish();
+    CHECK(!d.pending.empty());
+    const Chunk slow = d.pending.front();  // held in flight throughout
+    uint64_t max_seq = 0;
+    for (int it = 0; it < 200; ++it) {
+        d.publish();
+        // every chunk in flight (the slow one and the pending ones) has its
+        // own slot: sequence numbers within `ring` of the oldest
+        std::set<uint64_t> slots;
+        slots.insert(slow.seq % ring);
+        for (const Chunk &c : d.pending) {
+            if (c.seq == slow.seq) continue;
+            CHECK(c.seq - slow.seq < ring);
+            CHECK(slots.insert(c.seq % ring).second);
+            max_seq = std::max<uint64_t>(max_seq, c.seq);
+        }
+        // finish everything but the slow chunk
+        for (size_t k = 0; k < d.pending.size();) {
+            if (d.pending[k].seq == slow.seq) {
+                ++k;
+                continue;
+            }
+            d.done.insert(d.pending[k].seq);
+            d.pending.erase(d.pending.begin() + k);
+        }
+        d.collect();
+    }
+    CHECK(max_seq == slow.seq + ring - 1);  // publication stopped at the slot bound
+    CHECK(s.find(1)->state == RUNNING);
+    // once the slow chunk finishes, publication resumes and the shot completes
+    d.done.insert(slow.seq);
+    d.pending.erase(std::find_if(d.pending.begin(), d.pending.end(), [&](const Chunk &c) { return c.seq == slow.seq; }));
+    for (int it = 0; it < 100000 && s.find(1)->state != DONE; ++it) {
+        d.collect();
+        d.publish();
+        d.run(4, true);
+    }
+    d.collect();
+    CHECK(s.find(1)->state == DONE);
+}
+
 int main()
 {
     check_arena();
@@ -322,6 +372,7 @@ int main()
     check_fair_share();
     check_cancel();
     check_ring_sequence();
+    check_ring_slot_reuse();
     printf("all scheduler checks passed\n");
     return 0;
 }

@@ -171,12 +171,26 @@ def test_polarization_special_cases():
     # fully polarised, scattering in the plane of e (psi = 0): P = cos^2 2theta
     d = np.array([math.sin(0.7), 0.0, math.cos(0.7)])
     assert o.polarization(d, inc, e, 1.0) == pytest.approx(math.cos(0.7) ** 2, rel=1e-14)
-    # a tilted source: only the part of e perpendicular to it counts
-    inc2 = np.array([0.1, 0.0, 1.0]) / math.hypot(0.1, 1.0)
-    d = np.array([0.0, math.sin(0.4), math.cos(0.4)])
-    b = np.cross(inc2, np.array([1.0, 0.0, 0.0]) - inc2[0] * inc2)
-    b /= np.linalg.norm(b)
-    assert abs(d @ b) > 0.3
+    # a tilted source: only the part of e perpendicular to it counts.  For
+    # inc = (sin tau, 0, cos tau) and e = x that part is (cos tau, 0, -sin tau)
+    # and inc x e_perp = y, written out in closed form; d at angle a from inc
+    # and azimuth psi from e_perp gives P = (1 + cos^2 a - K cos 2psi sin^2 a)/2
+    tau = 0.3
+    inc2 = np.array([math.sin(tau), 0.0, math.cos(tau)])
+    ep = np.array([math.cos(tau), 0.0, -math.sin(tau)])
+    by = np.array([0.0, 1.0, 0.0])
+    for a, psi, K in [(0.5, 0.0, 1.0), (0.5, math.pi / 2, 1.0), (0.8, 0.6, 1.0), (0.35, 2.2, 0.6),
+                      (1.1, -0.9, 1.0)]:
+        d = math.cos(a) * inc2 + math.sin(a) * (math.cos(psi) * ep + math.sin(psi) * by)
+        expect = 0.5 * (1 + math.cos(a) ** 2 - K * math.cos(2 * psi) * math.sin(a) ** 2)
+        assert o.polarization(d, inc2, e, K) == pytest.approx(expect, rel=1e-14, abs=1e-15)
+    # psi = 0 with K = 1 is cos^2 2theta, psi = 90 deg is 1, for the tilted
+    # source too (measuring psi from e itself instead of its perpendicular
+    # part fails the psi = 90 deg case and the general ones above)
+    d0 = math.cos(0.5) * inc2 + math.sin(0.5) * ep
+    assert o.polarization(d0, inc2, e, 1.0) == pytest.approx(math.cos(0.5) ** 2, rel=1e-14)
+    d90 = math.cos(0.5) * inc2 + math.sin(0.5) * by
+    assert o.polarization(d90, inc2, e, 1.0) == pytest.approx(1.0, rel=1e-15)
 
 
 # ---------------------------------------------------------------- pin 9 ----
