@@ -308,12 +308,13 @@ struct xrt_fhkl {
 
 namespace {
 
-// 2^52 plus the byte offset of h = (0, 0, 0) relative to the table start
-// (an exact binary64 integer; see table_offset in the kernels).
-double biased_zero_offset(const xrt_fhkl *t, int64_t esize)
+// bias plus the element index of h = (0, 0, 0) in the padded table (an exact
+// binary64 integer; see table_offset in the kernels): 2^49 for the binary64
+// table, 2^50 for the binary32 one.
+double biased_zero_index(const xrt_fhkl *t, double bias)
 {
-    const int64_t o = -((int64_t)t->lo[0] * t->sa + (int64_t)t->lo[1] * t->sb + t->lo[2]) * esize;
-    return 4503599627370496.0 + (double)o;
+    const int64_t o = -((int64_t)t->lo[0] * t->sa + (int64_t)t->lo[1] * t->sb + t->lo[2]);
+    return bias + (double)o;
 }
 
 // True when every rint(h) of the shot provably lies in the padded box, so the
@@ -522,12 +523,10 @@ xrt_status make_plan(const xrt_detector *det, const xrt_beam *beam, const xrt_cr
         p.lo_d[i] = fhkl->lo[i];
         p.hi_d[i] = fhkl->hi[i];
     }
-    p.sa8 = 8.0 * fhkl->sa;
-    p.sb8 = 8.0 * fhkl->sb;
-    p.sa4 = 4.0 * fhkl->sa;
-    p.sb4 = 4.0 * fhkl->sb;
-    p.off8 = biased_zero_offset(fhkl, 8);
-    p.off4 = biased_zero_offset(fhkl, 4);
+    p.sa = (double)fhkl->sa;
+    p.sb = (double)fhkl->sb;
+    p.off64 = biased_zero_index(fhkl, 562949953421312.0);   // 2^49
+    p.off32 = biased_zero_index(fhkl, 1125899906842624.0);  // 2^50
     pl.clamp = !h_inside(det, box, beam, pl.host.data(), pl.n_rot, fhkl);
     const int64_t n_outer = (int64_t)p.O * p.O * p.T * p.n_src;
     p.split = split_factor(p.n_tiles, n_outer, n_outer * p.n_rot);

@@ -48,15 +48,17 @@ struct Params {
     double kahn;
     double norm;           // r_e^2 fluence scale / (O^2 n_phi n_mos)
     // structure factors: tables of F^2 with FHKL_PAD layers of F_default^2
-    // around the tabulated box.  The byte offset of entry h0 in the binary64
-    // (binary32) table is h0_a*sa8 + h0_b*sb8 + h0_c*8 + off8 - 2^52, exact in
-    // binary64 (sa4, ..., off4 likewise), for h0 in [lo_d, hi_d].
+    // around the tabulated box.  The element index of entry h0 is
+    // h0_a*sa + h0_b*sb + h0_c + zero with sa, sb the strides of the h and k
+    // axes and zero the index of h0 = 0; off64 = 2^49 + zero and
+    // off32 = 2^50 + zero carry the bias that turns the binary64 sum into the
+    // byte offset (see table_offset), for h0 in [lo_d, hi_d].
     const double *F2_64;
     const float *F2_32;
     uint32_t bytes64, bytes32;
     double lo_d[3], hi_d[3];
-    double sa8, sb8, sa4, sb4;
-    double off8, off4;
+    double sa, sb;
+    double off64, off32;
     // per-shot tables in device memory
     const double *mats;    // [n_rot][9]
     const double *src;     // [n_src][SRC_STRIDE]

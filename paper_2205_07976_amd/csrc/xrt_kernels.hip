@@ -57,14 +57,18 @@ __device__ __forceinline__ void sample_dir(const Params &p, int i_f, int i_s, in
 // dOmega * capture of a sample point: solid angle of the full pixel area
 // (sub-pixels are averaged by the final 1/O^2) times the Beer-Lambert
 // fraction absorbed in layer t, written exp(-a) (1 - exp(-(b - a))) with
-// expm1 so that thin layers keep their relative accuracy.
+// expm1 so that thin layers keep their relative accuracy.  The library's own
+// exp and expm1 (xrt_math.h) rather than the device libm's: those carry
+// special-case paths whose registers set the high-water mark of every kernel
+// that evaluates a sample point (113 against 73 VGPRs in the binary64 spots
+// kernel), for arguments that never occur here.
 __device__ __forceinline__ double sample_weight(const Params &p, const double d[3], double R, int t)
 {
     const double cosrho = (d[0] * p.odet[0] + d[1] * p.odet[1]) + d[2] * p.odet[2];
     const double domega = p.pixel * p.pixel * cosrho / (R * R);
     if (p.layer_dt == 0.0) return domega;
     const double l = p.atten_len * cosrho;
-    return domega * exp(-(double)t * p.layer_dt / l) * -expm1(-p.layer_dt / l);
+    return domega * exp_f64(-(double)t * p.layer_dt / l) * -expm1_f64(-p.layer_dt / l);
 }
 
 // S = (d - dir_j) / lambda_j, binary64.
@@ -95,23 +99,25 @@ __device__ __forceinline__ void miller(const double *M, const double S[3], doubl
 
 // Byte offset of the nearest reflection h0 in a padded F^2 table, from the
 // rounded indices hr (exact small integers in binary64):
-//   x = 2^52 + off + hr_a*sa + hr_b*sb + hr_c*esize
-// by three FMAs.  Every partial sum is an integer below 2^53, so x is exact,
-// and for 0 <= offset < 2^32 the low 32 bits of x are the offset itself (the
-// 2^52 bias fixes the exponent), which saves the float-to-int conversions.
-// CLAMP moves indices outside the padded box onto its border layer
-// (F_default^2); without it the host has proven every h0 of the shot inside.
+//   x = off + hr_c + hr_b*sb + hr_a*sa,   off = 2^B + (index of h0 = 0)
+// by one addition and two FMAs, each with one scalar operand (no register
+// copies).  Every partial sum is an integer below 2^51, so x is exact; for an
+// element index i in [0, 2^28), x = 2^B + i has the exponent of 2^B and a
+// mantissa field of i * 2^(52-B): with B = 49 the low 32 bits of x are 8 i,
+// the byte offset of a binary64 entry, with B = 50 they are 4 i, that of a
+// binary32 entry -- no float-to-int conversions.  CLAMP moves indices outside
+// the padded box onto its border layer (F_default^2); without it the host has
+// proven every h0 of the shot inside.
 template <bool CLAMP>
-__device__ __forceinline__ uint32_t table_offset(const Params &p, const double hr[3], double sa,
-                                                 double sb, double sc, double off)
+__device__ __forceinline__ uint32_t table_offset(const Params &p, const double hr[3], double off)
 {
     double v[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
         v[i] = CLAMP ? __builtin_fmin(__builtin_fmax(hr[i], p.lo_d[i]), p.hi_d[i]) : hr[i];
-    double x = __builtin_fma(v[2], sc, off);
-    x = __builtin_fma(v[1], sb, x);
-    x = __builtin_fma(v[0], sa, x);
+    double x = v[2] + off;
+    x = __builtin_fma(v[1], p.sb, x);
+    x = __builtin_fma(v[0], p.sa, x);
     return (uint32_t)__builtin_bit_cast(uint64_t, x);
 }
 
@@ -147,13 +153,14 @@ __device__ __forceinline__ double div_newton(double n, double d)
 }
 
 // ---------------------------------------------------------------------------
-// One term F^2 L^2, binary64.
+// One term F^2 L^2, binary64, added into s: s + (F^2 q) q for the sincg
+// ratio q, s + F^2 L^2 for the Gaussian factor L^2 (one FMA each).
 // ---------------------------------------------------------------------------
 template <int SHAPE, bool CLAMP>
-__device__ __forceinline__ double term_f64(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3])
+__device__ __forceinline__ double term_f64_add(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3],
+                                               double s)
 {
     double hr[3];
-    double L2;
     if (SHAPE == XRT_SHAPE_SINCG) {
         double num = 1.0, den = 1.0;
 #pragma unroll
@@ -166,7 +173,8 @@ __device__ __forceinline__ double term_f64(const Params &p, __amdgpu_buffer_rsrc
             den *= sinpi_reduced(fa);
         }
         const double q = div_newton(num, den);
-        L2 = q * q;
+        const double F2 = load_f64(tab, table_offset<CLAMP>(p, hr, p.off64));
+        return __builtin_fma(F2 * q, q, s);
     } else {
         double e = p.ln_n2;
 #pragma unroll
@@ -175,9 +183,9 @@ __device__ __forceinline__ double term_f64(const Params &p, __amdgpu_buffer_rsrc
             const double f = h[i] - hr[i];
             e = __builtin_fma(-p.gk[i], f * f, e);
         }
-        L2 = exp_f64(e);
+        const double F2 = load_f64(tab, table_offset<CLAMP>(p, hr, p.off64));
+        return __builtin_fma(F2, exp_f64(e), s);
     }
-    return load_f64(tab, table_offset<CLAMP>(p, hr, p.sa8, p.sb8, 8.0, p.off8)) * L2;
 }
 
 // One sincg term, mixed: h, f and g in binary64 (they decide the
@@ -198,7 +206,7 @@ __device__ __forceinline__ float term_mixed_sincg(const Params &p, __amdgpu_buff
         den *= sinpi_reduced(f);
     }
     const float q = num * __builtin_amdgcn_rcpf(den);
-    return load_f32(tab, table_offset<CLAMP>(p, hr, p.sa4, p.sb4, 4.0, p.off4)) * (q * q);
+    return load_f32(tab, table_offset<CLAMP>(p, hr, p.off32)) * (q * q);
 }
 
 // The Gaussian lattice exponent e = ln(Na^2 Nb^2 Nc^2) - sum_i gk_i f_i^2 of
@@ -297,13 +305,13 @@ struct RotSum {
         double h[3];
         miller(M, S, h);
         if constexpr (PREC == XRT_FP64) {
-            s64 += term_f64<SHAPE, CLAMP>(p, tab, h);
+            s64 = term_f64_add<SHAPE, CLAMP>(p, tab, h, s64);
         } else if constexpr (SHAPE == XRT_SHAPE_SINCG) {
             kahan_add(s, c, term_mixed_sincg<CLAMP>(p, tab, h));
         } else {
             double hr[3], f[3];
             const double e = gauss_exponent(p, h, hr, f);
-            const float F2 = load_f32(tab, table_offset<CLAMP>(p, hr, p.sa4, p.sb4, 4.0, p.off4));
+            const float F2 = load_f32(tab, table_offset<CLAMP>(p, hr, p.off32));
             const float k = gauss_rescale(m, e, F2);
             s *= k;
             c *= k;
@@ -735,12 +743,10 @@ __device__ __forceinline__ Params uniform_params(const Params &s)
     q.ln_n2 = uni(s.ln_n2);
     q.kahn = uni(s.kahn);
     q.norm = uni(s.norm);
-    q.sa8 = uni(s.sa8);
-    q.sb8 = uni(s.sb8);
-    q.sa4 = uni(s.sa4);
-    q.sb4 = uni(s.sb4);
-    q.off8 = uni(s.off8);
-    q.off4 = uni(s.off4);
+    q.sa = uni(s.sa);
+    q.sb = uni(s.sb);
+    q.off64 = uni(s.off64);
+    q.off32 = uni(s.off32);
     q.out_f64 = uni(s.out_f64);
     q.split = uni(s.split);
     return q;
@@ -1020,7 +1026,7 @@ __device__ __forceinline__ void grad_term_f64(const Params &p, __amdgpu_buffer_r
         f[i] = h - hr[i];
         e = __builtin_fma(-p.gk[i], f[i] * f[i], e);
     }
-    const double base = w * load_f64(tab, table_offset<CLAMP>(p, hr, p.sa8, p.sb8, 8.0, p.off8)) * exp_f64(e);
+    const double base = w * load_f64(tab, table_offset<CLAMP>(p, hr, p.off64)) * exp_f64(e);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const double dh = base * p.m2gk[i] * f[i];
@@ -1054,7 +1060,7 @@ __device__ __forceinline__ void grad_term_mixed(const Params &p, __amdgpu_buffer
     const double e = gauss_exponent(p, h, hr, fd);
 #pragma unroll
     for (int i = 0; i < 3; ++i) f[i] = (float)fd[i];
-    const float F2 = load_f32(tab, table_offset<CLAMP>(p, hr, p.sa4, p.sb4, 4.0, p.off4));
+    const float F2 = load_f32(tab, table_offset<CLAMP>(p, hr, p.off32));
     const float k = gauss_rescale(m, e, F2);
     if (k != 1.0f) {
 #pragma unroll

@@ -47,10 +47,12 @@ def test_stored_polynomial_error(kind, bound, degree):
 
 
 def exp_coefficients():
+    """Horner coefficients of exp(r) = 1 + r q(r), highest degree first: those
+    of exp_q, then the final 1 that exp_f64 adds."""
     src = open(HEADER).read()
-    body = src[src.index("double exp_f64(double e)"):]
-    body = body[body.index("double p = "):body.index("return __builtin_ldexp")]
-    return [mp.mpf(float(n)) for n in re.findall(r"[-+]?\d+\.\d+(?:e[-+]?\d+)?", body)]
+    body = src[src.index("double exp_q(double r)"):]
+    body = body[body.index("double p = "):body.index("}")]
+    return [mp.mpf(float(n)) for n in re.findall(r"[-+]?\d+\.\d+(?:e[-+]?\d+)?", body)] + [mp.mpf(1)]
 
 
 def test_stored_exp_polynomial_error():
