@@ -16,60 +16,103 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic VALU work of one pixel term (sincg inner loop), in FP32-lane-op
-# equivalents: a binary32 or 32-bit integer op counts 1, a binary64 op or a
-# conversion from binary64 counts 2 (binary64 runs at half the binary32 rate),
-# a binary32 transcendental counts 4 (quarter rate), a binary64 reciprocal 8.
-#   binary64: h = M S 12 ops; per axis 24 ops (rint, sub, max, N*f, rint, sub,
-#             two squares, 2 x 7 FMA Horner, two products); 4 products;
-#             reciprocal, one Newton step and a residual correction (rcp + 5);
-#             square and FMA accumulate 2; table offset 3 FMA
-#             -> 24 + 144 + 8 + 18 + 4 + 6 = 204
-#   mixed:    h 12 binary64 ops; per axis 6 binary64 ops, 2 conversions and 12
-#             binary32 ops; 4 products; rcp + mul; square and F^2 product;
-#             Kahan 4; table offset 3 binary64 FMA
-#             -> 24 + 84 + 4 + 5 + 2 + 4 + 6 = 129
-C_ALG = {"fp64": 204, "mixed": 129}
-# The background of an amorphous scatterer, per (pixel, sub-pixel, layer,
-# source) term, same units:
-#   binary64: d - dir 3 subs, |d - dir|^2 3 ops, its root (reciprocal square
-#             root 8 + 5 ops), times 1/(2 lambda) 1, clamp to the first knot 1,
-#             interval test 2 compares, interpolation 2, F^2 1, Kahn factor
-#             (3 dot products 9 + 5), w P 1, accumulate 1
-#             -> 6 + 6 + 18 + 2 + 2 + 4 + 4 + 2 + 28 + 4 = 76
-#   mixed:    binary32 throughout: d - dir from heads and tails 9, square 3,
-#             root 4, scale 1, clamp 1, compares 2, interpolation 2, F^2 1,
-#             Kahn factor 14, products 2, Kahan add 4
-#             -> 9 + 3 + 4 + 1 + 1 + 2 + 2 + 1 + 14 + 2 + 4 = 43
-C_ALG_BG = {"fp64": 76, "mixed": 43}
-# The refinement step (Gaussian shape), per pixel term, same units:
-#   forward binary64: h 12 ops, per axis rint, sub, square, FMA (12 ops), exp
-#             (clamp, scale, rint, 2 reduction FMAs, 11 Horner FMAs, ldexp,
-#             conversion: 18 ops), table offset 3 FMAs, F^2 L^2 and the
-#             accumulate 2 -> 24 + 24 + 36 + 6 + 4 = 94
-#   forward mixed: h 12 and the axes 12 binary64 ops (48), exponent add and
-#             conversion 4, binary32 exp 5, table offset 6, product 1, Kahan 4
-#             -> 48 + 4 + 5 + 6 + 1 + 4 = 68
-#   adjoint binary64: S' = Q^T S 9 ops, h 9, axes 12, table offset 3, exp 18,
-#             two products, per axis the h derivative (2 products, 3 FMAs) and
-#             the N derivative (product, 2 FMAs), dL/dscale 1
-#             -> 18 + 18 + 24 + 6 + 36 + 4 + 48 + 2 = 156
-#   adjoint mixed: S' 9 binary64 ops and 3 conversions (24), h 9 binary64 (18),
-#             per axis rint and sub in binary64, a conversion, square and FMA
-#             (24), table offset 6, binary32 exp and 2 products 7, derivatives
-#             24 binary32 ops, dL/dscale 1 -> 24 + 18 + 24 + 6 + 7 + 24 + 1 = 104
-C_ALG_REFINE = {"fwd": {"fp64": 94, "mixed": 68}, "bwd": {"fp64": 156, "mixed": 104}}
-# MI355X binary32 VALU peak: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz
-# = 78.64 T lane-op/s (157.3 TFLOP/s counting an FMA as 2 flops)
-PEAK_OPS = 256 * 4 * 32 * 2.4e9
-# HBM bytes per binary64 launch from the FETCH_SIZE / WRITE_SIZE counters,
-# each scaled by what it reads for a 1 GiB device copy (profiles/
-# spots_full_shot_counters.txt); set to None whenever the kernel changes.
-TRAFFIC_FP64 = 51.29e6
+# Algorithmic work of one pixel term of the method, frozen: floating-point
+# operations the definition itself prescribes, independent of how a kernel
+# implements them (each is derived in the design notes, "Roofline counts").
+# An addition, subtraction or multiplication is 1 flop, a fused multiply-add
+# 2, a division or square root 1; rint, compares, selects and the table
+# gather are not flops.  A function without a hardware instruction of the
+# required accuracy is priced as the minimax polynomial of the lowest degree
+# that reaches it, by Horner's rule: sin(pi x) on |x| <= 1/2 as x P(x^2) with
+# P of degree 7 for binary64 (16 flops), degree 4 for binary32 (10); exp on
+# the reduced range |r| <= ln2/2 with a degree-11 polynomial after a
+# Cody-Waite reduction for binary64 (27 flops); binary32 exp is the hardware
+# exp2 after a multiplication by log2(e) (2 flops).
+#   sincg, binary64: h = M S 15, f 3, g = N f - rint(N f) 6, six sines 96,
+#     ratio and square 6, F^2 L^2 and the sum 2                      -> 128
+#   sincg, mixed: binary64 h, f, g (24); binary32 six sines 60, ratio and
+#     square 6, F^2 L^2 1, Kahan sum 4 (71)
+#   Gaussian forward, binary64: h 15, f 3, exponent 9, exp 27, F^2 L^2 and
+#     the sum 2                                                      -> 56
+#   Gaussian forward, mixed: binary64 h, f, exponent and e - m (28); binary32
+#     exp 2, F^2 exp 1, Kahan sum 4 (7)
+#   adjoint, binary64: S' = Q^T S 15, h 15, f 3, exponent 9, exp 27, w F^2 exp
+#     2, per axis dL/dh (2 products, 3 FMA) and dL/dN (product, FMA, FMA) 39,
+#     dL/dscale 1                                                    -> 111
+#   adjoint, mixed: binary64 S', h, f, exponent, e - m (43); binary32 exp 2,
+#     w F^2 exp 2, derivatives 39, dL/dscale 1 (44)
+#   background, binary64: d - dir 3, its square 5, root 1, stol 1, the
+#     interpolation 3, F^2 1, Kahn factor (three dot products 15, 1 + c^2 2,
+#     x^2 - y^2 3, K term 2, half 1) 23, w P F^2 and the sum 3         -> 40
+#   background, mixed: the same in binary32 plus the Kahan sum's 3 more (43)
+FLOPS = {
+    "spots": {"fp64": {"f64": 128, "f32": 0}, "mixed": {"f64": 24, "f32": 71}},
+    "gauss_fwd": {"fp64": {"f64": 56, "f32": 0}, "mixed": {"f64": 28, "f32": 7}},
+    "adjoint": {"fp64": {"f64": 111, "f32": 0}, "mixed": {"f64": 43, "f32": 44}},
+    "background": {"fp64": {"f64": 40, "f32": 0}, "mixed": {"f64": 0, "f32": 43}},
+}
+# MI355X vector peaks (FMA = 2 flops): 256 CUs x 4 SIMDs x 2.4 GHz x 32
+# binary32 lanes (157.3 TFLOP/s) or 16 binary64 lanes (78.6 TFLOP/s) per cycle
+PEAK = {"f64": 256 * 4 * 16 * 2 * 2.4e9, "f32": 256 * 4 * 32 * 2 * 2.4e9}
+HBM_PEAK = 8.0e12
+
+
+def roofline_of(flops, terms_per_s):
+    """Achieved algorithmic TFLOP/s and the fraction of the vector roofline:
+    the time the flops of one term need at the binary64 and binary32 peaks,
+    times the terms per second (a mixed term is priced in both)."""
+    t_term = sum(flops[k] / PEAK[k] for k in flops)
+    total = sum(flops.values())
+    return {"achieved": total * terms_per_s / 1e12, "peak": total / t_term / 1e12,
+            "frac": terms_per_s * t_term, "flop_per_term": dict(flops)}
+
+
+# Issue efficiency (not a roofline): the implemented instruction sequence of
+# the binary64 and mixed sincg loops weighted by their measured issue cost on
+# gfx950, in binary32-lane-op units (binary32 op 1, binary64 op or conversion
+# 2, binary32 transcendental 4, binary64 reciprocal 8); it follows the
+# kernel, so a loop issued without stalls sits near 1.
+ISSUE_SLOTS = {"fp64": 204, "mixed": 129}
+ISSUE_PEAK = 256 * 4 * 32 * 2.4e9
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = [os.path.join(HERE, "paper_2205_07976_amd", "csrc", f)
+                  for f in ("xrt_kernels.hip", "xrt_math.h", "xrt_internal.h")]
+
+
+def kernel_src_sha():
+    """sha256 (16 hex digits) of the device sources: the key that ties a
+    committed counter summary to the kernels it measured."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fp:
+            h.update(fp.read())
+    return h.hexdigest()[:16]
+
+
+def profile_keys(name):
+    """The machine-readable figures of a committed counter summary under
+    profiles/ (its '# bench-keys {json}' line), or None if the kernels have
+    changed since its counters were taken or the file is missing."""
+    path = os.path.join(HERE, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fp:
+        for line in fp:
+            if line.startswith("# bench-keys "):
+                keys = json.loads(line[len("# bench-keys "):])
+                if keys.get("kernel_src_sha") == kernel_src_sha():
+                    keys["source"] = f"profiles/{name}"
+                    return keys
+                return None
+    return None
 
 
 def log(*a):
@@ -96,11 +139,49 @@ def time_form(shot, fh, precision, steps, warmup):
     return out, wall, ev_ms
 
 
+def host_threads():
+    """Host threads for the oracle: the CPUs this process may run on, capped
+    by OMP_NUM_THREADS when it is set (the share of the host that goes with
+    one GPU on a shared machine)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(n, 1)
+
+
+def host_description():
+    """What the CPU baseline ran on: the CPU model (lscpu), the logical CPUs
+    of the host (os.cpu_count), the ones this process may use (affinity) and
+    the cgroup CPU quota, if any."""
+    model = ""
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as fp:
+            q, per = fp.read().split()
+            quota = None if q == "max" else float(q) / float(per)
+    except Exception:
+        pass
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "cgroup_cpu_quota": quota, "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+
+
 def cpu_baseline(shot, budget_s=15.0):
-    """The oracle on a seeded pixel subset sized to about budget_s seconds."""
+    """The oracle on a seeded pixel subset sized to about budget_s seconds,
+    on every host thread this process may use."""
     import synth
     from oracle import oracle as o
-    cores = min(16, os.cpu_count() or 1)
+    cores = host_threads()
     n = 64
     while True:
         pix = synth.pixel_sample(shot, n, 99)
@@ -111,8 +192,11 @@ def cpu_baseline(shot, budget_s=15.0):
             break
         n = min(262144, max(2 * n, int(n * budget_s / max(dt, 1e-3))))
     terms = n * shot.terms_per_pixel
-    return {"value": terms / dt / 1e9, "unit": "Gterm/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} seeded pixels of the full-size shot ({terms:.3e} terms, {dt:.1f} s)"}
+    rate = terms / dt / 1e9
+    return {"value": rate, "unit": "Gterm/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} seeded pixels of the full-size shot ({terms:.3e} terms, {dt:.1f} s)",
+            "per_core": rate / cores, "host": host_description(),
+            "full_shot_s_extrapolated": shot.n_terms / (rate * 1e9)}
 
 
 def background_bench(shot, steps):
@@ -129,10 +213,9 @@ def background_bench(shot, steps):
     terms = shot.n_pixels * shot.oversample ** 2 * shot.n_layers * shot.n_src
     out = {"workload": f"water-like curve ({bg.n_knots} knots) over the full-size detector: "
                        "2463x2527 px, oversample 2, 3 layers, 100 sources = 1200 terms/px",
-           "terms": terms, "c_alg_per_term": C_ALG_BG, "peak": PEAK_OPS / 1e12,
-           "unit": "T fp32-lane-op/s"}
+           "terms": terms, "unit": "TFLOP/s"}
     pix = synth.pixel_sample(shot, 256, 77)
-    ref = o.background(shot, bg, pix, nthreads=min(16, os.cpu_count() or 1))
+    ref = o.background(shot, bg, pix, nthreads=host_threads())
     n = max(steps, 5)
     for prec in ("fp64", "mixed"):
         img = torch.empty(shot.roi_shape, dtype=torch.float64 if prec == "fp64" else torch.float32, device="cuda")
@@ -146,11 +229,11 @@ def background_bench(shot, steps):
         torch.cuda.synchronize()
         ms = sum(a.elapsed_time(b) for a, b in evs) / n
         x = img.cpu().numpy()[pix[:, 1], pix[:, 0]].astype(np.float64)
-        ach = C_ALG_BG[prec] * terms / (ms * 1e-3)
-        out[prec] = {"ms": ms, "Gterm_s": terms / ms / 1e6, "achieved": ach / 1e12, "frac": ach / PEAK_OPS,
+        rf = roofline_of(FLOPS["background"][prec], terms / (ms * 1e-3))
+        out[prec] = {"ms": ms, "Gterm_s": terms / ms / 1e6, **rf,
                      "max_rel_err": float(np.max(np.abs(x - ref) / ref)), "err_sample": "256 seeded pixels"}
-        log(f"background {prec}: {ms:.2f} ms, {terms / ms / 1e6:.0f} Gterm/s, frac {ach / PEAK_OPS:.3f}")
-    cores = min(16, os.cpu_count() or 1)
+        log(f"background {prec}: {ms:.2f} ms, {terms / ms / 1e6:.0f} Gterm/s, frac {rf['frac']:.3f}")
+    cores = host_threads()
     sample = synth.pixel_sample(shot, 262144, 78)
     t0 = time.perf_counter()
     o.background(shot, bg, sample, nthreads=cores)
@@ -223,7 +306,7 @@ def mixed_error(shot, img32):
     import synth
     from oracle import oracle as o
     pix = synth.pixel_sample(shot, 256, 2024)
-    ref = o.simulate(shot, pix, nthreads=min(16, os.cpu_count() or 1))
+    ref = o.simulate(shot, pix, nthreads=host_threads())
     x = img32[pix[:, 1], pix[:, 0]].astype(np.float64)
     r = np.abs(x - ref) / ref
     return float(r.max()), float(np.sqrt(np.mean(r * r)))
@@ -253,7 +336,7 @@ def adjoint_bench(steps):
     base = shot.replace(U=np.eye(3), cell=(shot.U @ shot.cell.T).T.copy())
     terms = len(origins) * size[0] * size[1] * shot.terms_per_pixel
     out = {"workload": "512 ROIs of 32x32 px around predicted spots, Gaussian N=20, 60000 terms/px",
-           "terms_per_pass": terms, "c_alg_per_term": C_ALG_REFINE}
+           "terms_per_pass": terms}
     grads = {}
     for prec in ("fp64", "mixed"):
         img = xrt.simulate_rois(base, fh, origins, size, precision=prec, out_dtype=torch.float64)
@@ -275,11 +358,11 @@ def adjoint_bench(steps):
         grads[prec] = g.cpu().numpy()
         out[prec] = {"fwd_ms": fms, "bwd_ms": bms, "fwd_Gterm_s": terms / fms / 1e6,
                      "bwd_Gterm_s": terms / bms / 1e6,
-                     "fwd_frac": C_ALG_REFINE["fwd"][prec] * terms / (fms * 1e-3) / PEAK_OPS,
-                     "bwd_frac": C_ALG_REFINE["bwd"][prec] * terms / (bms * 1e-3) / PEAK_OPS,
+                     "fwd_roofline": roofline_of(FLOPS["gauss_fwd"][prec], terms / (fms * 1e-3)),
+                     "bwd_roofline": roofline_of(FLOPS["adjoint"][prec], terms / (bms * 1e-3)),
                      "loss": float(((img - target) ** 2).sum())}
-        log(f"adjoint {prec}: forward {fms:.1f} ms (frac {out[prec]['fwd_frac']:.3f}), "
-            f"backward {bms:.1f} ms (frac {out[prec]['bwd_frac']:.3f})")
+        log(f"adjoint {prec}: forward {fms:.1f} ms (frac {out[prec]['fwd_roofline']['frac']:.3f}), "
+            f"backward {bms:.1f} ms (frac {out[prec]['bwd_roofline']['frac']:.3f})")
     d = np.abs(grads["mixed"] - grads["fp64"])
     out["grad_fp64"] = grads["fp64"].tolist()
     out["mixed_vs_fp64_max_diff_over_max"] = [float(d[sl].max() / np.abs(grads["fp64"][sl]).max())
@@ -287,39 +370,120 @@ def adjoint_bench(steps):
     return out
 
 
-def serving_bench(n_cap=60, n_open=150, load=0.8):
-    """The served shot stream: independent shots with a random orientation,
-    log-uniform ROI (64..2463 x 64..2527 px), 1-100 sources, 1-200 domains,
-    N in [5, 40], the full-size detector and shared table, mixed precision.
-    Closed loop (all submitted at once) gives the capacity; then Poisson
-    arrivals at `load` x capacity give the latency percentiles."""
-    import numpy as np
+def standalone_times(shots, fh, precision, tag):
+    """Each shot's time as one standalone xrt_simulate call (HIP events on the
+    launch stream around the call), one call per shot after one warm-up; the
+    images go to one reused buffer."""
+    import torch
+    from paper_2205_07976_amd import xrt
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    buf = torch.empty(max(s.n_pixels for s in shots), dtype=dt, device="cuda")
+    xrt.simulate(shots[0], fh, precision=precision, out=buf[:shots[0].n_pixels].view(shots[0].roi_shape))
+    torch.cuda.synchronize()
+    out = np.empty(len(shots))
+    batch = 100
+    for b0 in range(0, len(shots), batch):
+        evs = []
+        for s in shots[b0:b0 + batch]:
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            xrt.simulate(s, fh, precision=precision, out=buf[:s.n_pixels].view(s.roi_shape))
+            b.record()
+            evs.append((a, b))
+        torch.cuda.synchronize()
+        out[b0:b0 + len(evs)] = [a.elapsed_time(b) * 1e-3 for a, b in evs]
+        log(f"  standalone {tag}: {b0 + len(evs)}/{len(shots)} shots timed")
+    return out
+
+
+def latency_stats(res, shots, t_alone, offered_rate=None):
+    """serve.summarize plus the slowdown: each shot's latency over its own
+    standalone time (1 = served as fast as alone on an idle device)."""
+    from paper_2205_07976_amd import serve
+    out = serve.summarize(res, shots, offered_rate)
+    slow = res["latency"] / t_alone
+    out["p50_slowdown"] = float(np.percentile(slow, 50))
+    out["p99_slowdown"] = float(np.percentile(slow, 99))
+    out["mean_slowdown"] = float(np.mean(slow))
+    return out
+
+
+def serving_bench(n_pool=1000, n_cap=200, n_fp64=60, loads=(0.5, 0.8, 0.95)):
+    """The served shot stream (independent shots: random orientation,
+    log-uniform ROI 64..2463 x 64..2527 px, 1-100 sources, 1-200 domains,
+    N in [5, 40], the full-size detector and shared table).  A pool of n_pool
+    shots is timed standalone first (mixed); n_cap of them submitted at once
+    give the capacity; then all n_pool arrive as a Poisson stream at each
+    load x capacity (a seeded order per load).  Latency is submit -> result
+    ready on the server's clock; slowdown is latency over the shot's
+    standalone time.  Also: the capacity of a binary64 server against the
+    binary64 standalone calls of the same shots, and the mixed capacity with
+    the water-like background added to every image."""
     import synth
     from paper_2205_07976_amd import serve, xrt
     base = synth.full_shot()
     fh = xrt.Fhkl.from_shot(base)
     rng = np.random.default_rng(4)
-    cap_shots = [synth.served_shot(rng, base.F, base.hkl_min) for _ in range(n_cap)]
-    open_shots = [synth.served_shot(rng, base.F, base.hkl_min) for _ in range(n_open)]
+    pool = [synth.served_shot(rng, base.F, base.hkl_min) for _ in range(n_pool)]
+    terms = np.array([float(s.n_terms) for s in pool])
+    log(f"serving: pool of {n_pool} shots, {terms.sum():.3e} terms (mean {terms.mean():.3e})")
+    t_mixed = standalone_times(pool, fh, "mixed", "mixed")
+
+    def progress(tag, n):
+        def cb(i, t, count=[0]):
+            count[0] += 1
+            if count[0] % 100 == 0 or count[0] == n:
+                log(f"  {tag}: {count[0]}/{n} shots done")
+        return cb
+
+    out = {"workload": "served stream: log-uniform ROI, 1-100 sources, 1-200 domains, N in [5,40], "
+                       "full-size detector and table, mixed",
+           "pool": {"shots": n_pool, "terms": float(terms.sum()),
+                    "standalone_mixed_s": float(t_mixed.sum()),
+                    "standalone_mixed_Gterm_s": float(terms.sum() / t_mixed.sum() / 1e9)}}
     srv = xrt.Server(fh, hbm_budget=16 << 30, max_resident=64, precision="mixed")
-    # warm-up: the persistent kernel's first launch
-    serve.run_stream(srv, cap_shots[:2], np.zeros(2))
-    closed = serve.summarize(serve.run_stream(srv, cap_shots, np.zeros(n_cap)), cap_shots)
-    rate = load * closed["images_per_s"]
-    arr = serve.poisson_arrivals(np.random.default_rng(6), n_open, rate)
-    opened = serve.summarize(serve.run_stream(srv, open_shots, arr), open_shots, rate)
+    serve.run_stream(srv, pool[:2], np.zeros(2))  # the persistent kernel's first launch
+    cap = pool[:n_cap]
+    res = serve.run_stream(srv, cap, np.zeros(n_cap), on_done=progress("capacity", n_cap))
+    closed = latency_stats(res, cap, t_mixed[:n_cap])
+    closed["standalone_s"] = float(t_mixed[:n_cap].sum())
+    closed["vs_standalone"] = closed["standalone_s"] / closed["makespan_s"]
+    out["closed_loop"] = closed
+    log(f"serving: capacity {closed['images_per_s']:.2f} img/s, {closed['Gterm_per_s']:.0f} Gterm/s, "
+        f"{closed['vs_standalone']:.3f} of the standalone calls")
+    for load in loads:
+        order = np.random.default_rng(int(round(load * 100))).permutation(n_pool)
+        shots = [pool[i] for i in order]
+        rate = load * closed["images_per_s"]
+        arr = serve.poisson_arrivals(np.random.default_rng(int(round(load * 1000))), n_pool, rate)
+        res = serve.run_stream(srv, shots, arr, on_done=progress(f"load {load:.2f}", n_pool), timeout=900.0)
+        st = latency_stats(res, shots, t_mixed[order], rate)
+        st["load"] = load
+        out[f"poisson_{load:.2f}"] = st
+        log(f"serving at {load:.2f} x capacity: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms, "
+            f"slowdown p50 {st['p50_slowdown']:.2f} p99 {st['p99_slowdown']:.2f}, {st['Gterm_per_s']:.0f} Gterm/s")
     srv.close()
-    log(f"serving: capacity {closed['images_per_s']:.1f} img/s ({closed['Gterm_per_s']:.0f} Gterm/s); "
-        f"at {load:.2f} load p50 {opened['p50_ms']:.1f} ms p99 {opened['p99_ms']:.1f} ms")
-    # the same closed loop with the water-like background added to every image
+    # binary64: served capacity against standalone binary64 calls
+    sub = pool[:n_fp64]
+    t64 = standalone_times(sub, fh, "fp64", "fp64")
+    srv = xrt.Server(fh, hbm_budget=16 << 30, max_resident=64, precision="fp64")
+    serve.run_stream(srv, sub[:2], np.zeros(2))
+    c64 = serve.summarize(serve.run_stream(srv, sub, np.zeros(n_fp64)), sub)
+    srv.close()
+    c64["standalone_s"] = float(t64.sum())
+    c64["standalone_Gterm_s"] = float(terms[:n_fp64].sum() / t64.sum() / 1e9)
+    c64["vs_standalone"] = c64["standalone_s"] / c64["makespan_s"]
+    out["closed_loop_fp64"] = c64
+    log(f"serving binary64: {c64['Gterm_per_s']:.0f} Gterm/s served, {c64['standalone_Gterm_s']:.0f} standalone "
+        f"({c64['vs_standalone']:.3f})")
+    # the mixed closed loop with the water-like background on every image
     srv = xrt.Server(fh, hbm_budget=16 << 30, max_resident=64, precision="mixed",
                      background=synth.water_background())
-    serve.run_stream(srv, cap_shots[:2], np.zeros(2))
-    with_bg = serve.summarize(serve.run_stream(srv, cap_shots, np.zeros(n_cap)), cap_shots)
+    serve.run_stream(srv, sub[:2], np.zeros(2))
+    out["closed_loop_with_background"] = serve.summarize(serve.run_stream(srv, sub, np.zeros(n_fp64)), sub)
     srv.close()
-    log(f"serving with the background: capacity {with_bg['images_per_s']:.1f} img/s")
-    return {"workload": "served stream: log-uniform ROI, 1-100 sources, 1-200 domains, N in [5,40], mixed",
-            "closed_loop": closed, "poisson": opened, "load": load, "closed_loop_with_background": with_bg}
+    log(f"serving with the background: {out['closed_loop_with_background']['images_per_s']:.2f} img/s")
+    return out
 
 
 def serving_io_bench(n_shots=40, write_ms=20.0, writers=4, budgets=(256 << 20, 64 << 20)):
@@ -366,47 +530,40 @@ def serving_io_bench(n_shots=40, write_ms=20.0, writers=4, budgets=(256 << 20, 6
     return out
 
 
-def serving_sweep(n_cap=200, n_open=1000, loads=(0.5, 0.8, 0.95), small_budget=256 << 20):
-    """The served stream at several offered loads: capacity from n_cap shots
-    submitted at once, then n_open Poisson arrivals at each load x capacity;
-    finally the capacity again under a small HBM budget, which admits fewer
-    shots at once.  Several minutes of GPU time: not part of the default run."""
-    import numpy as np
+def served_region_bench(steps, side=1024):
+    """One side x side region of the full-size shot served alone (the only
+    shot on the server, so the persistent kernel runs its chunks and nothing
+    else) against the standalone call on the same region, both precisions:
+    the per-term cost of the served kernel, free of the stream's mix."""
+    import torch
     import synth
     from paper_2205_07976_amd import serve, xrt
-    base = synth.full_shot()
-    fh = xrt.Fhkl.from_shot(base)
-    rng = np.random.default_rng(14)
-
-    def progress(tag, n):
-        def cb(i, t, count=[0]):
-            count[0] += 1
-            if count[0] % 100 == 0 or count[0] == n:
-                log(f"  {tag}: {count[0]}/{n} shots done")
-        return cb
-
-    out = {"workload": "served stream: log-uniform ROI, 1-100 sources, 1-200 domains, N in [5,40], mixed"}
-    for name, budget in (("budget_16GiB", 16 << 30), (f"budget_{small_budget >> 20}MiB", small_budget)):
-        srv = xrt.Server(fh, hbm_budget=budget, max_resident=64, precision="mixed")
-        cap_shots = [synth.served_shot(rng, base.F, base.hkl_min) for _ in range(n_cap)]
-        serve.run_stream(srv, cap_shots[:2], np.zeros(2))
-        closed = serve.summarize(serve.run_stream(srv, cap_shots, np.zeros(n_cap),
-                                                  on_done=progress(f"{name} capacity", n_cap)), cap_shots)
-        log(f"{name}: capacity {closed['images_per_s']:.2f} img/s ({closed['Gterm_per_s']:.0f} Gterm/s)")
-        res = {"closed_loop": closed}
-        if name == "budget_16GiB":
-            for load in loads:
-                shots = [synth.served_shot(rng, base.F, base.hkl_min) for _ in range(n_open)]
-                rate = load * closed["images_per_s"]
-                arr = serve.poisson_arrivals(np.random.default_rng(int(load * 100)), n_open, rate)
-                opened = serve.summarize(serve.run_stream(srv, shots, arr, on_done=progress(f"load {load}", n_open)),
-                                         shots, rate)
-                log(f"{name} at {load:.2f} load: p50 {opened['p50_ms']:.1f} ms p99 {opened['p99_ms']:.1f} ms, "
-                    f"{opened['Gterm_per_s']:.0f} Gterm/s")
-                res[f"poisson_{load:.2f}"] = opened
+    shot = synth.full_shot()
+    fh = xrt.Fhkl.from_shot(shot)
+    f0, s0 = 1231 - side // 2, 1263 - side // 2
+    reg = shot.replace(roi=(f0, f0 + side, s0, s0 + side))
+    out = {"workload": f"{side}x{side} region of the full-size shot ({reg.n_terms:.3e} terms)"}
+    n = max(steps, 3)
+    for prec in ("fp64", "mixed"):
+        _, _, ev = time_form(reg, fh, prec, n, 1)
+        alone = sum(ev) / len(ev) * 1e-3
+        srv = xrt.Server(fh, hbm_budget=1 << 30, max_resident=4, precision=prec)
+        serve.run_stream(srv, [reg], np.zeros(1))
+        lat = []
+        for _ in range(n):
+            r = serve.run_stream(srv, [reg], np.zeros(1))
+            lat.append(float(r["latency"][0]))
         srv.close()
-        out[name] = res
+        torch.cuda.synchronize()
+        served = float(np.median(lat))
+        out[prec] = {"standalone_ms": alone * 1e3, "served_ms": served * 1e3, "served_vs_standalone": alone / served}
+        log(f"served region {side}^2 {prec}: standalone {alone * 1e3:.1f} ms, served {served * 1e3:.1f} ms "
+            f"({alone / served:.3f})")
     return out
+
+
+SECTIONS = ("mixed", "small_roi", "background", "ensemble", "adjoint", "served_region", "serving", "serving_io", "cpu")
+DEFAULT_SECTIONS = ("mixed", "small_roi", "background", "ensemble", "adjoint", "served_region", "serving", "cpu")
 
 
 def main():
@@ -414,14 +571,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
-    ap.add_argument("--no-adjoint", action="store_true", help="skip the regions-of-interest adjoint")
-    ap.add_argument("--no-background", action="store_true", help="skip the background of an amorphous scatterer")
-    ap.add_argument("--no-serve", action="store_true", help="skip the served shot stream")
-    ap.add_argument("--serve-sweep", action="store_true",
-                    help="also serve 1000 Poisson shots at 0.5, 0.8 and 0.95 x capacity and measure the "
-                         "capacity under a 256 MiB budget (several minutes)")
+    ap.add_argument("--only", default="",
+                    help="comma-separated sections to run after the binary64 full shot (default: "
+                         + ",".join(DEFAULT_SECTIONS) + "; also available: serving_io)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="finish with one device-to-device copy of this many MiB (a kernel of known "
                          "traffic that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -429,6 +581,11 @@ def main():
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); shots would be sharded "
               "one per GPU with no exchange, which this build does not launch.", file=sys.stderr)
+        return 2
+    sections = set(args.only.split(",")) - {""} if args.only else set(DEFAULT_SECTIONS)
+    unknown = sections - set(SECTIONS)
+    if unknown:
+        print(f"unknown sections {sorted(unknown)}; choose from {SECTIONS}", file=sys.stderr)
         return 2
 
     import torch
@@ -445,7 +602,8 @@ def main():
     ms = 1e3 * wall / args.steps
     kern_ms = sum(ev) / len(ev)
     value = terms / (wall / args.steps) / 1e9
-    ach = C_ALG["fp64"] * terms / (kern_ms * 1e-3)
+    rf = roofline_of(FLOPS["spots"]["fp64"], terms / (kern_ms * 1e-3))
+    ctr = profile_keys("spots_full_shot_counters.txt")
     res = {
         "metric": "pixel-term evaluations/s (G/s) vs FP32 VALU peak; p50/p99 shot latency",
         "value": value, "unit": "Gterm/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -454,52 +612,62 @@ def main():
         "config": {"workload": "full-size shot, binary64: 2463x2527 px, oversample 2, 3 layers, "
                                "100 sources, 50 mosaic domains, sincg N=20, Fhkl [-60,60]^3",
                    "pixels": shot.n_pixels, "terms_per_pixel": shot.terms_per_pixel, "terms": terms},
-        "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_OPS / 1e12,
-                     "unit": "T fp32-lane-op/s", "frac": ach / PEAK_OPS, "traffic": TRAFFIC_FP64,
+        "roofline": {"bound": "alu", "achieved": rf["achieved"], "peak": rf["peak"], "unit": "TFLOP/s",
+                     "frac": rf["frac"], "traffic": ctr["fp64"]["traffic_bytes"] if ctr else None,
                      "kernel": "spots_kernel<FP64,SINCG>", "kernel_ms": kern_ms,
-                     "c_alg_per_term": C_ALG["fp64"]},
+                     "flop_per_term": rf["flop_per_term"],
+                     "counters": ctr["fp64"] if ctr else None,
+                     "counters_source": ctr["source"] if ctr else None,
+                     "issue_efficiency": ISSUE_SLOTS["fp64"] * terms / (kern_ms * 1e-3) / ISSUE_PEAK},
     }
     log(f"fp64: {ms:.1f} ms/step (events {kern_ms:.1f} ms), {value:.1f} Gterm/s, "
-        f"roofline frac {ach / PEAK_OPS:.3f}")
+        f"{rf['achieved']:.1f} algorithmic TFLOP/s, roofline frac {rf['frac']:.3f}")
 
-    if not args.no_mixed:
+    if "mixed" in sections:
         img32, wall32, ev32 = time_form(shot, fh, "mixed", args.steps, args.warmup)
         k32 = sum(ev32) / len(ev32)
         v32 = terms / (wall32 / args.steps) / 1e9
-        a32 = C_ALG["mixed"] * terms / (k32 * 1e-3)
+        rf32 = roofline_of(FLOPS["spots"]["mixed"], terms / (k32 * 1e-3))
         emax, erms = mixed_error(shot, img32.cpu().numpy())
         res["mixed"] = {"value": v32, "unit": "Gterm/s", "ms_per_step": 1e3 * wall32 / args.steps,
-                        "kernel_ms": k32, "frac": a32 / PEAK_OPS, "speedup_vs_fp64": v32 / value,
+                        "kernel_ms": k32, "roofline": rf32,
+                        "counters": ctr["mixed"] if ctr else None,
+                        "issue_efficiency": ISSUE_SLOTS["mixed"] * terms / (k32 * 1e-3) / ISSUE_PEAK,
+                        "speedup_vs_fp64": v32 / value,
                         "max_rel_err": emax, "rms_rel_err": erms, "err_sample": "256 seeded pixels"}
-        log(f"mixed: {1e3 * wall32 / args.steps:.1f} ms/step, {v32:.1f} Gterm/s, max rel err {emax:.2e}")
+        log(f"mixed: {1e3 * wall32 / args.steps:.1f} ms/step, {v32:.1f} Gterm/s, frac {rf32['frac']:.3f}, "
+            f"max rel err {emax:.2e}")
 
-    # a small region of the same shot: its sums are split over many
-    # workgroups (a 64 x 64 region is only 16 tiles)
-    small = shot.replace(roi=(1200, 1264, 1250, 1314))
-    res["small_roi"] = {"workload": "64x64 region of the full-size shot (2.46e8 terms, split sums)"}
-    for prec in ("fp64", "mixed"):
-        _, wall_s, ev_s = time_form(small, fh, prec, max(args.steps, 5), 1)
-        ms_s = sum(ev_s) / len(ev_s)
-        res["small_roi"][prec] = {"ms": ms_s, "Gterm_s": small.n_terms / ms_s / 1e6}
-        log(f"small ROI {prec}: {ms_s:.2f} ms, {small.n_terms / ms_s / 1e6:.0f} Gterm/s")
+    if "small_roi" in sections:
+        # a small region of the same shot: its sums are split over many
+        # workgroups (a 64 x 64 region is only 16 tiles)
+        small = shot.replace(roi=(1200, 1264, 1250, 1314))
+        res["small_roi"] = {"workload": "64x64 region of the full-size shot (2.46e8 terms, split sums)"}
+        for prec in ("fp64", "mixed"):
+            _, wall_s, ev_s = time_form(small, fh, prec, max(args.steps, 5), 1)
+            ms_s = sum(ev_s) / len(ev_s)
+            res["small_roi"][prec] = {"ms": ms_s, "Gterm_s": small.n_terms / ms_s / 1e6}
+            log(f"small ROI {prec}: {ms_s:.2f} ms, {small.n_terms / ms_s / 1e6:.0f} Gterm/s")
 
-    if not args.no_background:
+    if "background" in sections:
         res["background"] = background_bench(shot, args.steps)
         res["background"]["image_fp64_ms"] = kern_ms + res["background"]["fp64"]["ms"]
-
-    if not args.no_background:
+        bgc = profile_keys("background_full_detector_counters.txt")
+        res["background"]["counters"] = bgc
+    if "ensemble" in sections:
         res["ensemble"] = ensemble_bench(shot, args.steps)
-
-    if not args.no_adjoint:
+    if "adjoint" in sections:
         res["adjoint"] = adjoint_bench(args.steps)
-
-    if not args.no_serve:
+        res["adjoint"]["counters"] = profile_keys("grad_rois_counters.txt")
+    if "served_region" in sections:
+        res["served_region"] = served_region_bench(args.steps)
+        res["served_region"]["counters"] = profile_keys("serve_region_counters.txt")
+    if "serving" in sections:
         res["serving"] = serving_bench()
-        res["p50_shot_latency_ms"] = res["serving"]["poisson"]["p50_ms"]
-        res["p99_shot_latency_ms"] = res["serving"]["poisson"]["p99_ms"]
+        res["p50_shot_latency_ms"] = res["serving"]["poisson_0.80"]["p50_ms"]
+        res["p99_shot_latency_ms"] = res["serving"]["poisson_0.80"]["p99_ms"]
+    if "serving_io" in sections:
         res["serving_io"] = serving_io_bench()
-    if args.serve_sweep:
-        res["serving_sweep"] = serving_sweep()
 
     if args.copy_mib:
         n = args.copy_mib * (1 << 20) // 4
@@ -510,7 +678,7 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: {args.copy_mib} MiB read + {args.copy_mib} MiB written")
 
-    if not args.no_cpu:
+    if "cpu" in sections:
         res["cpu_baseline"] = cpu_baseline(shot)
         log(f"cpu oracle: {res['cpu_baseline']}")
     print(json.dumps(res), flush=True)
