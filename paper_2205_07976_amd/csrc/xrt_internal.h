@@ -90,6 +90,7 @@ constexpr int SERVE_MAX_ROT = 256;   // spindle steps x mosaic domains per serve
 constexpr int SERVE_MAX_SRC = 128;   // sources per served shot
 constexpr int SERVE_MAX_CHUNK = 64;  // tiles (or tile parts) per chunk
 constexpr int SERVE_MAX_SPLIT = 64;  // parts per pixel sum
+constexpr uint32_t SERVE_RING = 1u << 16;  // chunk records and done flags (a power of two)
 enum { CHUNK_COMPUTE = 0, CHUNK_REDUCE = 1, CHUNK_BACKGROUND = 2 };
 
 struct ShotDesc {
@@ -126,9 +127,8 @@ struct ServeCtrl {          // pinned host memory, written by the host
 
 struct ServeArgs {
     const ServeCtrl *ctrl;
-    const ServeChunk *ring;   // [cap], pinned host memory
-    uint32_t *done;           // [cap], pinned host memory
-    uint32_t cap;
+    const ServeChunk *ring;   // [SERVE_RING], pinned host memory
+    uint32_t *done;           // [SERVE_RING], pinned host memory
     unsigned long long *next; // chunks claimed so far (device memory)
     unsigned int *busy;       // workgroups holding a chunk (device memory, 0 at launch)
     unsigned int *exiting;    // set once the kernel is idle: every workgroup leaves

@@ -97,6 +97,17 @@ __device__ __forceinline__ void miller(const double *M, const double S[3], doubl
         h[i] = __builtin_fma(M[3 * i + 2], S[2], M[3 * i] * S[0] + M[3 * i + 1] * S[1]);
 }
 
+// h_i = fma(M_i2, S_2, fma(M_i1, S_1, M_i0 S_0)): the mixed form, which has
+// no bit-exact contract with the oracle, forms h in binary64 with three
+// operations per index instead of four (the same accuracy: two roundings
+// fewer).  Negating M negates h exactly, as in miller.
+__device__ __forceinline__ void miller_fused(const double *M, const double S[3], double h[3])
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        h[i] = __builtin_fma(M[3 * i + 2], S[2], __builtin_fma(M[3 * i + 1], S[1], M[3 * i] * S[0]));
+}
+
 // Byte offset of the nearest reflection h0 in a padded F^2 table, from the
 // rounded indices hr (exact small integers in binary64):
 //   x = off + hr_c + hr_b*sb + hr_a*sa,   off = 2^B + (index of h0 = 0)
@@ -299,11 +310,23 @@ struct RotSum {
     double s64 = 0.0;
     float s = 0.0f, c = 0.0f;
     double m = -__builtin_inf();  // mixed Gaussian: reference exponent
+    // h = M S by the sequence of this precision
+    static __device__ __forceinline__ void hkl(const double M[9], const double S[3], double h[3])
+    {
+        if constexpr (PREC == XRT_FP64)
+            miller(M, S, h);
+        else
+            miller_fused(M, S, h);
+    }
     __device__ __forceinline__ void add(const Params &p, __amdgpu_buffer_rsrc_t tab, const double M[9],
                                         const double S[3])
     {
         double h[3];
-        miller(M, S, h);
+        hkl(M, S, h);
+        add_h(p, tab, h);
+    }
+    __device__ __forceinline__ void add_h(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3])
+    {
         if constexpr (PREC == XRT_FP64) {
             s64 = term_f64_add<SHAPE, CLAMP>(p, tab, h, s64);
         } else if constexpr (SHAPE == XRT_SHAPE_SINCG) {
@@ -337,26 +360,24 @@ __device__ __forceinline__ void load9(double m[9], const double *src)
 }
 
 // Without PF the matrix of term r is read where it is used (scalar loads in
-// the standalone kernel).  With PF (tables in LDS) two register sets take
-// turns: the reads of matrix r + 1 are issued before term r is evaluated, and
-// the loop is unrolled by two so that no register copies are needed between
-// terms.
+// the standalone kernel).  With PF (tables in LDS) the matrix of term r is
+// dead once h = M S is formed, so the reads of matrix r + 1 are issued into
+// the same registers right then and complete while the rest of term r is
+// evaluated: one register set, no copies between terms.
 template <int PREC, int SHAPE, bool CLAMP, bool PF>
 __device__ __forceinline__ void rot_sum(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *mats,
                                         const double S[3], RotSum<PREC, SHAPE, CLAMP> &acc)
 {
     const int n = p.n_rot;
     if (PF) {
-        double ma[9], mb[9];
-        load9(ma, mats);
-        int r = 0;
-        for (; r + 1 < n; r += 2) {
-            load9(mb, mats + 9 * (r + 1));
-            acc.add(p, tab, ma, S);
-            load9(ma, mats + 9 * (r + 2 < n ? r + 2 : r + 1));
-            acc.add(p, tab, mb, S);
+        double m[9];
+        load9(m, mats);
+        for (int r = 0; r < n; ++r) {
+            double h[3];
+            acc.hkl(m, S, h);
+            load9(m, mats + 9 * (r + 1 < n ? r + 1 : r));
+            acc.add_h(p, tab, h);
         }
-        if (r < n) acc.add(p, tab, ma, S);
     } else {
         for (int r = 0; r < n; ++r) acc.add(p, tab, mats + 9 * r, S);
     }
@@ -555,6 +576,23 @@ struct BgRow {
     R dir[3], lo[3], e[3], b[3], hil, w;
 };
 
+// The binary32 row with direction tails made from a binary64 row, as the
+// host makes the standalone kernel's copies: head (float)x, tail
+// (float)(x - (double)(float)x).
+__device__ __forceinline__ void bg_row32(BgRow<float> &r, const double *src)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double x = src[SRC_DIR + i];
+        r.dir[i] = (float)x;
+        r.lo[i] = (float)(x - (double)r.dir[i]);
+        r.e[i] = (float)src[SRC_E + i];
+        r.b[i] = (float)src[SRC_B + i];
+    }
+    r.hil = (float)src[SRC_HIL];
+    r.w = (float)src[SRC_WEIGHT];
+}
+
 template <typename R>
 __device__ __forceinline__ void bg_row(BgRow<R> &r, const R *src, bool tails)
 {
@@ -569,15 +607,19 @@ __device__ __forceinline__ void bg_row(BgRow<R> &r, const R *src, bool tails)
     r.w = src[SRC_WEIGHT];
 }
 
-// Kahn factor of one source row, P = (1 + c^2 - K (x^2 - y^2)) / 2 as in the
-// spots kernel, by fused products.
+// Twice the Kahn factor of one source row, 2P = 1 + c^2 - K (x^2 - y^2) as
+// in the spots kernel, by fused products; c = d.dir comes from the square
+// q = |d - dir|^2 the curve lookup has formed, c = 1 - q/2 (for unit vectors
+// |d - dir|^2 = 2 - 2 d.dir; the norms of d and dir differ from 1 by a few
+// units of roundoff, which moves c by as much).  The factor 1/2 is applied
+// once per sample point.
 template <typename R>
-__device__ __forceinline__ R bg_polarization(const BgRow<R> &s, const R d[3], R K)
+__device__ __forceinline__ R bg_polarization2(const BgRow<R> &s, const R d[3], R K, R q)
 {
-    const R c = fma_r(d[2], s.dir[2], fma_r(d[1], s.dir[1], d[0] * s.dir[0]));
+    const R c = fma_r(R(-0.5), q, R(1));
     const R x = fma_r(d[2], s.e[2], fma_r(d[1], s.e[1], d[0] * s.e[0]));
     const R y = fma_r(d[2], s.b[2], fma_r(d[1], s.b[1], d[0] * s.b[0]));
-    return R(0.5) * fma_r(-K, fma_r(x, x, -(y * y)), fma_r(c, c, R(1)));
+    return fma_r(-K, fma_r(x, x, -(y * y)), fma_r(c, c, R(1)));
 }
 
 template <int PREC>
@@ -587,8 +629,11 @@ using BgReal = typename std::conditional<PREC == XRT_FP64, double, float>::type;
 // sub-pixels, layers and sources of the standalone and the served kernels
 // alike (kt: the curve records, in LDS or global memory; srcs and srcs32: the
 // binary64 rows and their binary32 copies with direction tails), so a pixel
-// has the same bits through either.
-template <int PREC>
+// has the same bits through either.  LEAN (the served kernel, whose register
+// budget the spots sum sets): each row is read where it is used, with no
+// next-row prefetch or unrolling, and the binary32 rows are made from the
+// binary64 ones (srcs32 unused).
+template <int PREC, bool LEAN = false>
 __device__ __forceinline__ double bg_pixel_sum(const Params &p, const BgKnot<BgReal<PREC>> *kt, const double *srcs,
                                                const float *srcs32, int i_f, int i_s)
 {
@@ -609,15 +654,18 @@ __device__ __forceinline__ double bg_pixel_sum(const Params &p, const BgKnot<BgR
                     BgRow<double> cur, nxt;
                     bg_row(cur, srcs, false);
                     for (int j = 0; j < p.n_src; ++j) {
-                        bg_row(nxt, srcs + SRC_STRIDE * (j + 1 < p.n_src ? j + 1 : j), false);
+                        if (LEAN)
+                            bg_row(cur, srcs + SRC_STRIDE * j, false);
+                        else
+                            bg_row(nxt, srcs + SRC_STRIDE * (j + 1 < p.n_src ? j + 1 : j), false);
                         const double e0 = d[0] - cur.dir[0], e1 = d[1] - cur.dir[1], e2 = d[2] - cur.dir[2];
-                        const double len = root_small(__builtin_fma(e2, e2, __builtin_fma(e1, e1, e0 * e0)));
-                        const double F = bg_curve(kt, ck, k, x0, len * cur.hil);
-                        const double P = bg_polarization(cur, d, p.kahn);
-                        sub = __builtin_fma(cur.w * P, F * F, sub);
-                        cur = nxt;
+                        const double q = __builtin_fma(e2, e2, __builtin_fma(e1, e1, e0 * e0));
+                        const double F = bg_curve(kt, ck, k, x0, root_small(q) * cur.hil);
+                        const double P2 = bg_polarization2(cur, d, p.kahn, q);
+                        sub = __builtin_fma(cur.w * P2, F * F, sub);
+                        if (!LEAN) cur = nxt;
                     }
-                    acc64 = __builtin_fma(wgeo, sub, acc64);
+                    acc64 = __builtin_fma(0.5 * wgeo, sub, acc64);
                 } else {
                     // d - dir cancels near the direct beam: d and dir are
                     // each split into a binary32 head and the binary32 rest,
@@ -627,19 +675,22 @@ __device__ __forceinline__ double bg_pixel_sum(const Params &p, const BgKnot<BgR
                     const float dlo[3] = {(float)(d[0] - (double)d32[0]), (float)(d[1] - (double)d32[1]),
                                           (float)(d[2] - (double)d32[2])};
                     float s = 0.0f, c = 0.0f;
-#pragma unroll 2
+#pragma unroll LEAN ? 1 : 2
                     for (int j = 0; j < p.n_src; ++j) {
                         BgRow<float> cur;
-                        bg_row(cur, srcs32 + SRC32_STRIDE * j, true);
+                        if (LEAN)
+                            bg_row32(cur, srcs + SRC_STRIDE * j);
+                        else
+                            bg_row(cur, srcs32 + SRC32_STRIDE * j, true);
                         const float e0 = (d32[0] - cur.dir[0]) + (dlo[0] - cur.lo[0]);
                         const float e1 = (d32[1] - cur.dir[1]) + (dlo[1] - cur.lo[1]);
                         const float e2 = (d32[2] - cur.dir[2]) + (dlo[2] - cur.lo[2]);
-                        const float len = root_small(__builtin_fmaf(e2, e2, __builtin_fmaf(e1, e1, e0 * e0)));
-                        const float F = bg_curve(kt, ck, k, x0, len * cur.hil);
-                        const float P = bg_polarization(cur, d32, (float)p.kahn);
-                        kahan_add(s, c, cur.w * P * (F * F));
+                        const float q = __builtin_fmaf(e2, e2, __builtin_fmaf(e1, e1, e0 * e0));
+                        const float F = bg_curve(kt, ck, k, x0, root_small(q) * cur.hil);
+                        const float P2 = bg_polarization2(cur, d32, (float)p.kahn, q);
+                        kahan_add(s, c, cur.w * P2 * (F * F));
                     }
-                    kahan_add(acc, accc, (float)wgeo * (s - c));
+                    kahan_add(acc, accc, (float)(0.5 * wgeo) * (s - c));
                 }
             }
     return PREC == XRT_FP64 ? acc64 : (double)(acc - accc);
@@ -690,9 +741,16 @@ hipError_t launch_background(const BgParams &b, int precision, hipStream_t strea
 // run the same per-pixel sum as the standalone kernel and set the chunk's done
 // flag.  Like the standalone kernel, a shot whose every rint(h) the host has
 // proven inside the padded table takes the clamp-free table index (both give
-// the same bits where the clamp-free one is valid); the kernel keeps within 168
-// VGPRs (3 waves per SIMD) with the next matrix's LDS reads in flight during
-// each term.  The kernel leaves
+// the same bits where the clamp-free one is valid).  Registers: the next
+// matrix's LDS reads are in flight during each term in the one register set
+// of the current matrix; values that are the same for the whole workgroup
+// (descriptor fields, chunk bounds, arena offsets) are moved into scalar
+// registers; background chunks read the source rows where they are used and
+// make their binary32 copies on the fly (the same values the host makes for
+// the standalone kernel); the lane index of the staging and chunk loops is
+// opaque to the compiler, so the addresses it forms are not kept through the
+// whole kernel.  So the kernel fits 4 waves per SIMD (mixed sincg) or 3 (the
+// other forms) without spilling to scratch.  The kernel leaves
 // only when the whole device is idle: no workgroup holds a chunk, nothing
 // published is unclaimed and no chunk finished for idle_ticks; the first
 // workgroup to see that raises the exit flag and all workgroups leave together
@@ -714,6 +772,12 @@ __device__ __forceinline__ double uni(double x)
 }
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni(uint64_t x)
+{
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return lo | (hi << 32);
+}
 
 __device__ __forceinline__ Params uniform_params(const Params &s)
 {
@@ -768,12 +832,11 @@ __device__ __forceinline__ long long serve_claim(const ServeArgs &a)
 }
 
 template <int PREC, int SHAPE>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PREC == XRT_MIXED ? 4 : 3))) void serve_kernel(const ServeArgs a)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PREC == XRT_MIXED && SHAPE == XRT_SHAPE_SINCG ? 4 : 3))) void serve_kernel(const ServeArgs a)
 {
     __shared__ ShotDesc sd;
     __shared__ double smats[9 * SERVE_MAX_ROT];
     __shared__ double ssrc[SRC_STRIDE * SERVE_MAX_SRC];
-    __shared__ float ssrc32[SRC32_STRIDE * SERVE_MAX_SRC];  // background chunks, mixed
     __shared__ long long s_claim;
     __shared__ uint64_t s_off, s_have_off;
     __shared__ int32_t s_tile0, s_ntiles, s_kind;
@@ -803,7 +866,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PREC == X
                 c = serve_claim(a);
                 if (c >= 0) {
                     __hip_atomic_fetch_add(a.busy, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const ServeChunk *ch = a.ring + (uint64_t)c % a.cap;
+                    const ServeChunk *ch = a.ring + ((uint64_t)c & (SERVE_RING - 1));
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the chunk and its descriptor
                     s_off = __hip_atomic_load(&ch->desc_off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     s_tile0 = __hip_atomic_load(&ch->tile0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -845,15 +908,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PREC == X
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 const_cast<char *>(a.hdesc) + (ok ? off : 0), 0, (int)(room < 0x7fffffffull ? room : 0x7fffffffull),
                 0x00020000);
-            for (int i = threadIdx.x; i < (int)(sizeof(ShotDesc) / 4); i += BLOCK)
+            // the lane index as an opaque value: the staging addresses are
+            // formed here, not kept in registers through the whole kernel
+            int tid = threadIdx.x;
+            __asm__ volatile("" : "+v"(tid));
+            for (int i = tid; i < (int)(sizeof(ShotDesc) / 4); i += BLOCK)
                 reinterpret_cast<uint32_t *>(&sd)[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, 4 * i, 0, 0);
             __syncthreads();
             // bound every loop extent of the descriptor
             const int n_rot = min(max(sd.p.n_rot, 0), SERVE_MAX_ROT);
             const int n_src = min(max(sd.p.n_src, 0), SERVE_MAX_SRC);
-            for (int i = threadIdx.x; i < 9 * n_rot; i += BLOCK)
+            for (int i = tid; i < 9 * n_rot; i += BLOCK)
                 smats[i] = load_f64(rs, (uint32_t)(sd.mats_rel + 8 * (uint64_t)i));
-            for (int i = threadIdx.x; i < SRC_STRIDE * n_src; i += BLOCK)
+            for (int i = tid; i < SRC_STRIDE * n_src; i += BLOCK)
                 ssrc[i] = load_f64(rs, (uint32_t)(sd.src_rel + 8 * (uint64_t)i));
             __syncthreads();
             if (threadIdx.x == 0) {
@@ -871,53 +938,40 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PREC == X
         const Params p = uniform_params(sd.p);
         const int roi_f0 = uni(sd.roi_f0), roi_s0 = uni(sd.roi_s0);
         const int clamp = uni(sd.clamp);
-        const int n_units = min(max(s_ntiles, 0), SERVE_MAX_CHUNK);
+        const int n_units = uni(min(max(s_ntiles, 0), SERVE_MAX_CHUNK));
+        const int tile0 = uni(s_tile0), kind = uni(s_kind);
         const int split = p.split;
         const int n_outer = p.O * p.O * p.T * p.n_src;
-        const uint64_t img = sd.image_off, part = sd.partial_off;
-        if (PREC == XRT_MIXED && s_kind == CHUNK_BACKGROUND) {
-            // binary32 copies of the source rows with direction tails, made
-            // as the host makes them for the standalone background kernel
-            for (int i = threadIdx.x; i < p.n_src * SRC32_STRIDE; i += BLOCK) {
-                const int j = i / SRC32_STRIDE, q = i - j * SRC32_STRIDE;
-                const double *row = ssrc + SRC_STRIDE * j;
-                float v = 0.0f;
-                if (q < SRC_STRIDE) {
-                    v = (float)row[q];
-                } else if (q >= SRC32_DIR_LO && q < SRC32_DIR_LO + 3) {
-                    const double x = row[SRC_DIR + q - SRC32_DIR_LO];
-                    v = (float)(x - (double)(float)x);
-                }
-                ssrc32[i] = v;
-            }
-            __syncthreads();
-        }
+        const uint64_t img = uni(sd.image_off), part = uni(sd.partial_off);
+        const uint64_t image_bytes = uni(sd.image_bytes), partial_bytes = uni(sd.partial_bytes);
+        int ctid = threadIdx.x;  // opaque, as in the staging above
+        __asm__ volatile("" : "+v"(ctid));
         for (int i = 0; i < n_units; ++i) {
             // compute chunk: unit = tile * split + part; reduce chunk: unit = tile
-            const int unit = s_tile0 + i;
-            const int t = s_kind == CHUNK_COMPUTE ? unit / split : unit;
-            const int k = s_kind == CHUNK_COMPUTE ? unit - t * split : 0;
+            const int unit = tile0 + i;
+            const int t = kind == CHUNK_COMPUTE ? unit / split : unit;
+            const int k = kind == CHUNK_COMPUTE ? unit - t * split : 0;
             const int tf = t % p.tiles_f, ts = t / p.tiles_f;
-            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+            const int lane = ctid & 63, wave = ctid >> 6;
             const int lf = tf * TILE + (wave & 1) * 8 + (lane & 7);
             const int ls = ts * TILE + (wave >> 1) * 8 + (lane >> 3);
             const bool live = lf < p.roi_nf && ls < p.roi_ns;
             // partial sums of this tile and lane: [tile][part][lane] binary64
-            const uint64_t pq = part + 8 * (((uint64_t)t * split) * BLOCK + threadIdx.x);
+            const uint64_t pq = part + 8 * (((uint64_t)t * split) * BLOCK + ctid);
             const bool parts_ok = part <= a.arena_bytes && pq + 8 * ((uint64_t)(split - 1) * BLOCK + 1) <= a.arena_bytes &&
-                                  8 * (((uint64_t)t * split + split) * BLOCK) <= sd.partial_bytes;
-            if (s_kind == CHUNK_BACKGROUND) {
+                                  8 * (((uint64_t)t * split + split) * BLOCK) <= partial_bytes;
+            if (kind == CHUNK_BACKGROUND) {
                 // the server's background added into the complete image, as
                 // xrt_simulate_background with accumulate does
                 if (!a.bg_knots) continue;
                 const int i_f = roi_f0 + (lf < p.roi_nf ? lf : p.roi_nf - 1);
                 const int i_s = roi_s0 + (ls < p.roi_ns ? ls : p.roi_ns - 1);
-                const double bsum = bg_pixel_sum<PREC>(p, static_cast<const BgKnot<BgReal<PREC>> *>(a.bg_knots), ssrc,
-                                                       ssrc32, i_f, i_s);
+                const double bsum = bg_pixel_sum<PREC, true>(p, static_cast<const BgKnot<BgReal<PREC>> *>(a.bg_knots), ssrc,
+                                                             nullptr, i_f, i_s);
                 const double bval = uni(sd.bg_norm) * bsum;
                 const uint64_t besz = p.out_f64 ? 8 : 4;
                 const uint64_t bo = besz * ((uint64_t)ls * (uint64_t)p.roi_nf + (uint64_t)lf);
-                if (live && bo + besz <= sd.image_bytes && img <= a.arena_bytes && bo + besz <= a.arena_bytes - img) {
+                if (live && bo + besz <= image_bytes && img <= a.arena_bytes && bo + besz <= a.arena_bytes - img) {
                     if (p.out_f64) {
                         double *q = reinterpret_cast<double *>(a.arena + img + bo);
                         *q = *q + bval;
@@ -929,7 +983,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PREC == X
                 continue;
             }
             double sum;
-            if (s_kind == CHUNK_COMPUTE) {
+            if (kind == CHUNK_COMPUTE) {
                 const int i_f = roi_f0 + (lf < p.roi_nf ? lf : p.roi_nf - 1);
                 const int i_s = roi_s0 + (ls < p.roi_ns ? ls : p.roi_ns - 1);
                 const int q0 = part_begin(k, split, n_outer), q1 = part_begin(k + 1, split, n_outer);
@@ -945,7 +999,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PREC == X
             const double val = p.norm * sum;
             const uint64_t esz = p.out_f64 ? 8 : 4;
             const uint64_t o = esz * ((uint64_t)ls * (uint64_t)p.roi_nf + (uint64_t)lf);
-            if (live && o + esz <= sd.image_bytes && img <= a.arena_bytes && o + esz <= a.arena_bytes - img) {
+            if (live && o + esz <= image_bytes && img <= a.arena_bytes && o + esz <= a.arena_bytes - img) {
                 if (p.out_f64)
                     *reinterpret_cast<double *>(a.arena + img + o) = val;
                 else
@@ -955,7 +1009,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PREC == X
         __threadfence_system();
         __syncthreads();
         if (threadIdx.x == 0) {
-            __hip_atomic_store(a.done + (uint64_t)c % a.cap, s_seq1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(a.done + ((uint64_t)c & (SERVE_RING - 1)), s_seq1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
             __hip_atomic_store(a.last_done, (unsigned long long)__builtin_amdgcn_s_memrealtime(), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(a.busy, -1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

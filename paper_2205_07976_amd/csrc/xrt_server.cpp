@@ -54,7 +54,7 @@ using xrt::host::hip_fail;
 namespace {
 
 using xrt::sched::align_up;
-constexpr uint32_t RING = 1u << 16;
+constexpr uint32_t RING = xrt::SERVE_RING;
 static_assert(xrt::sched::PHASE_COMPUTE == xrt::CHUNK_COMPUTE && xrt::sched::PHASE_REDUCE == xrt::CHUNK_REDUCE &&
                   xrt::sched::PHASE_BACKGROUND == xrt::CHUNK_BACKGROUND,
               "chunk kinds");
@@ -321,7 +321,6 @@ xrt_status launch(xrt_server *s)
     a.ctrl = s->ctrl;
     a.ring = s->ring;
     a.done = s->done;
-    a.cap = RING;
     a.next = s->dev_ctl;
     a.last_done = s->dev_ctl + 1;
     a.busy = reinterpret_cast<unsigned int *>(s->dev_ctl + 2);

@@ -28,6 +28,8 @@ pytestmark = pytest.mark.gpu
 from paper_2205_07976_amd import xrt  # noqa: E402
 
 PI_LD = np.longdouble("3.14159265358979323846264338327950288")
+SINPI64_ULP = 4.0   # bounds derived in the module docstring
+SINPI32_ULP = 3.0
 
 
 def say(*a):
@@ -40,24 +42,35 @@ def ulp64(r):
 
 
 def test_sinpi_binary64_against_extended_precision():
+    """10^8 points: 6 seeded batches of 2^24 uniform on [0, 1/2] plus edge
+    points, against sin in 80-bit extended precision (64-bit significand: the
+    reference's own error is below 2^-11 binary64 ulp)."""
     assert np.finfo(np.longdouble).nmant >= 63, "needs 80-bit long double on the host"
     rng = np.random.default_rng(11)
-    x = rng.uniform(0.0, 0.5, 1 << 22)
     edge = np.array([0.0, 5e-324, 1e-300, 2.0 ** -32, 1e-8, 0.125, 0.25, 0.375, 0.4999999999999999, 0.5])
-    x = np.concatenate([edge, x])
-    xd = torch.from_numpy(x).cuda()
-    s64, _ = xrt.sinpi(xd)
-    s = s64.cpu().numpy()
-    ref = np.sin(PI_LD * x.astype(np.longdouble))
-    err = np.abs(s.astype(np.longdouble) - ref)
-    nz = ref != 0
-    ulps = np.zeros_like(x)
-    ulps[nz] = (err[nz] / ulp64(ref[nz]).astype(np.longdouble)).astype(np.float64)
-    say("binary64 sinpi: max", ulps.max(), "ulp at x =", x[np.argmax(ulps)], "mean", ulps.mean())
-    assert s[0] == 0.0 and np.all(ulps <= 4.0)
-    # odd symmetry is exact: x * P(x^2) with x^2 even
-    sn, _ = xrt.sinpi(-xd)
-    assert torch.equal(sn, -s64)
+    worst, where, n = 0.0, 0.0, 0
+    for b in range(6):
+        x = rng.uniform(0.0, 0.5, 1 << 24)
+        if b == 0:
+            x = np.concatenate([edge, x])
+        xd = torch.from_numpy(x).cuda()
+        s64, _ = xrt.sinpi(xd)
+        s = s64.cpu().numpy()
+        ref = np.sin(PI_LD * x.astype(np.longdouble))
+        err = np.abs(s.astype(np.longdouble) - ref)
+        nz = ref != 0
+        ulps = np.zeros_like(x)
+        ulps[nz] = (err[nz] / ulp64(ref[nz]).astype(np.longdouble)).astype(np.float64)
+        if b == 0:
+            assert s[0] == 0.0
+            # odd symmetry is exact: x * P(x^2) with x^2 even
+            sn, _ = xrt.sinpi(-xd)
+            assert torch.equal(sn, -s64)
+        if ulps.max() > worst:
+            worst, where = float(ulps.max()), float(x[np.argmax(ulps)])
+        n += len(x)
+    say("binary64 sinpi: max", worst, "ulp at x =", where, f"({n} points)")
+    assert worst <= SINPI64_ULP
 
 
 def test_sinpi_binary32_exhaustive():
@@ -79,7 +92,7 @@ def test_sinpi_binary32_exhaustive():
         if m > worst:
             worst, where = m, float(x[int(u.argmax())])
     say("binary32 sinpi: max", worst, "ulp at x =", where, f"({top + 1 - first} inputs)")
-    assert worst <= 3.0
+    assert worst <= SINPI32_ULP
 
 
 def test_exp_binary64_against_extended_precision():
