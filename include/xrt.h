@@ -184,6 +184,27 @@ xrt_status xrt_simulate(const xrt_detector *det, const xrt_beam *beam,
                         int32_t precision, void *dev_image, int32_t out_dtype,
                         int32_t accumulate, void *stream);
 
+/* xrt_simulate for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, validation, kernels and bits as xrt_simulate; instead of
+ * taking device memory stream-ordered for the shot's tables and the split
+ * sums' partial sums, the call uses a static device array of
+ * XRT_NOALLOC_SCRATCH_BYTES that every device the library runs on holds
+ * until the process ends (tables in its first MiB, partial sums after them).
+ * It calls no device allocator (no hipMalloc, hipMallocAsync, hipFree or
+ * hipFreeAsync); the tables are copied into the array on `stream`.
+ * The array is shared by every call on a device and keeps the last call's
+ * contents: calls that overlap on one device (different streams, or other
+ * threads) race and must be serialised by the caller; calls one after
+ * another on one stream are ordered.
+ * Errors: as xrt_simulate; ERANGE when the shot's tables exceed 1 MiB
+ * (9 n_phi n_mos + 12 n_src + 1 doubles) or the device ordinal is >= 64. */
+#define XRT_NOALLOC_SCRATCH_BYTES ((1u << 20) + (8u << 20))
+xrt_status xrt_simulate_noalloc(const xrt_detector *det, const xrt_beam *beam,
+                                const xrt_crystal *xtal, const xrt_fhkl *fhkl,
+                                int32_t precision, void *dev_image, int32_t out_dtype,
+                                int32_t accumulate, void *stream);
+
 /* Simulate n_roi regions of interest of one shot, all roi_nf x roi_ns pixels,
  * in one launch (the per-crystal refinement of section II works on the
  * pixels around predicted Bragg spots).

@@ -13,6 +13,7 @@
 #include <climits>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -442,6 +443,11 @@ xrt_status xrt_cell_mats(const xrt_crystal *xtal, double *host_out)
 
 }  // extern "C"
 
+// The static device memory of xrt_simulate_noalloc (its layout and size are
+// described there); host code reaches it only through the per-device address
+// that hipGetSymbolAddress returns.
+static __device__ __align__(256) char scratch[XRT_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 // Everything a launch over a list of equal-size regions of interest needs:
@@ -551,26 +557,73 @@ xrt_status check_call(int32_t precision, int32_t dtype, const void *ptr, const c
     return XRT_OK;
 }
 
+// Bytes of the split sums' partial sums [tile][part][lane] of a plan (0
+// when its sums are not split).
+size_t partial_bytes(const Plan &pl)
+{
+    return pl.p.split > 1 ? sizeof(double) * (size_t)pl.p.n_tiles * pl.p.split * 256 : 0;
+}
+
+// Uploads the plan's tables and launches the spots kernel (and the reduce
+// kernel of split sums).  Device memory for the tables and the partial sums:
+// `work` (tables at its start, partial sums at part_at bytes) when given,
+// else one stream-ordered allocation freed stream-ordered after the launch.
 xrt_status run_spots(Plan &pl, int32_t precision, void *dev_image, int32_t out_dtype, int32_t accumulate,
-                     hipStream_t s, const char *who)
+                     hipStream_t s, const char *who, char *work = nullptr, size_t part_at = 0)
 {
     pl.p.image = dev_image;
     pl.p.out_f64 = out_dtype == XRT_F64;
     pl.p.accumulate = accumulate;
-    double *tables = nullptr;
     const size_t bytes = sizeof(double) * pl.host.size();
-    // split sums: partial sums [tile][part][lane] after the tables
-    const size_t part_bytes = pl.p.split > 1 ? sizeof(double) * (size_t)pl.p.n_tiles * pl.p.split * 256 : 0;
-    HIP_TRY(hipMallocAsync((void **)&tables, bytes + part_bytes, s), "hipMallocAsync");
+    const size_t part_bytes = partial_bytes(pl);
+    double *tables = reinterpret_cast<double *>(work);
+    double *part = reinterpret_cast<double *>(work + part_at);
+    if (!work) {
+        HIP_TRY(hipMallocAsync((void **)&tables, bytes + part_bytes, s), "hipMallocAsync");
+        part = tables + pl.host.size();
+    }
     hipError_t e = hipMemcpyAsync(tables, pl.host.data(), bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
         bind_tables(pl, tables);
-        pl.p.partial = part_bytes ? tables + pl.host.size() : nullptr;
+        pl.p.partial = part_bytes ? part : nullptr;
         e = xrt::launch_spots(pl.p, precision, pl.clamp, s);
     }
-    hipError_t e2 = hipFreeAsync(tables, s);
+    hipError_t e2 = work ? hipSuccess : hipFreeAsync(tables, s);
     if (e != hipSuccess) return hip_fail(e, who);
     if (e2 != hipSuccess) return hip_fail(e2, who);
+    return XRT_OK;
+}
+
+// Device memory of xrt_simulate_noalloc: the shot's tables in the first
+// NOALLOC_TABLE_BYTES, the split sums' partial sums after them.  A split
+// sum has fewer than 2 * SPLIT_TARGET (tile, part) units of 256 lanes, so
+// its partial sums fit in NOALLOC_PART_BYTES.  Each device holds its own
+// copy from the library's load until the process ends.
+constexpr size_t NOALLOC_TABLE_BYTES = (size_t)1 << 20;
+constexpr size_t NOALLOC_PART_BYTES = (size_t)2 * SPLIT_TARGET * 256 * sizeof(double);
+constexpr size_t NOALLOC_BYTES = NOALLOC_TABLE_BYTES + NOALLOC_PART_BYTES;
+static_assert(NOALLOC_BYTES == XRT_NOALLOC_SCRATCH_BYTES, "scratch size of include/xrt.h");
+
+// The device address of `scratch` on each device, looked up once per device
+// with that device current (host code never uses the symbol itself).
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch[NOALLOC_MAX_DEVICES] = {};
+
+xrt_status scratch_of_device(int dev, char **out)
+{
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(XRT_ERANGE, "device %d beyond the %d devices of the static scratch table", dev,
+                    NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(XRT_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch[dev] = static_cast<char *>(ptr);
+    }
+    *out = g_scratch[dev];
     return XRT_OK;
 }
 
@@ -660,6 +713,36 @@ xrt_status xrt_simulate(const xrt_detector *det, const xrt_beam *beam, const xrt
                         false, pl)))
         return st;
     return run_spots(pl, precision, dev_image, out_dtype, accumulate, (hipStream_t)stream, "xrt_simulate");
+}
+
+xrt_status xrt_simulate_noalloc(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal,
+                                const xrt_fhkl *fhkl, int32_t precision, void *dev_image, int32_t out_dtype,
+                                int32_t accumulate, void *stream)
+{
+    xrt_status st;
+    if ((st = check_call(precision, out_dtype, dev_image, "dev_image"))) return st;
+    if (accumulate != 0 && accumulate != 1) return fail(XRT_EINVAL, "accumulate must be 0 or 1");
+    if (!det) return fail(XRT_EINVAL, "detector is NULL");
+    if ((st = check_detector(det))) return st;
+    if ((st = check_roi(det, det->roi_f0, det->roi_f1, det->roi_s0, det->roi_s1, 0))) return st;
+    const int32_t origin[2] = {det->roi_f0, det->roi_s0};
+    Plan pl;
+    if ((st = make_plan(det, beam, xtal, fhkl, 1, origin, det->roi_f1 - det->roi_f0, det->roi_s1 - det->roi_s0,
+                        false, pl)))
+        return st;
+    const size_t tb = sizeof(double) * pl.host.size(), pb = partial_bytes(pl);
+    if (tb > NOALLOC_TABLE_BYTES)
+        return fail(XRT_ERANGE, "xrt_simulate_noalloc: the shot's tables take %zu bytes, above the %zu of the "
+                    "static scratch (9 n_phi n_mos + 12 n_src + 1 doubles)", tb, NOALLOC_TABLE_BYTES);
+    if (pb > NOALLOC_PART_BYTES)
+        return fail(XRT_ERANGE, "xrt_simulate_noalloc: partial sums of %zu bytes above the %zu of the static "
+                    "scratch", pb, NOALLOC_PART_BYTES);
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    char *work = nullptr;
+    if ((st = scratch_of_device(dev, &work))) return st;
+    return run_spots(pl, precision, dev_image, out_dtype, accumulate, (hipStream_t)stream, "xrt_simulate_noalloc",
+                     work, NOALLOC_TABLE_BYTES);
 }
 
 xrt_status xrt_simulate_rois(const xrt_detector *det, const xrt_beam *beam, const xrt_crystal *xtal,

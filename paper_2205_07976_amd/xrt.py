@@ -105,7 +105,7 @@ SYMBOLS = ("xrt_version", "xrt_last_error", "xrt_fhkl_create", "xrt_fhkl_destroy
            "xrt_simulate", "xrt_simulate_rois", "xrt_backward_rois", "xrt_server_create",
            "xrt_server_destroy", "xrt_server_submit", "xrt_server_progress", "xrt_server_info",
            "xrt_server_image", "xrt_server_host_image", "xrt_server_release", "xrt_server_cancel", "xrt_cell_mats", "xrt_trace_terms", "xrt_sinpi", "xrt_exp",
-           "xrt_simulate_background", "xrt_add_image", "xrt_add_images")
+           "xrt_simulate_background", "xrt_add_image", "xrt_add_images", "xrt_simulate_noalloc")
 XRT_SHOT_QUEUED, XRT_SHOT_RUNNING, XRT_SHOT_DONE = 0, 1, 2
 
 
@@ -123,6 +123,7 @@ def load():
     lib.xrt_fhkl_destroy.argtypes = [C.c_void_p]
     lib.xrt_simulate.argtypes = [C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal), C.c_void_p,
                                  C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
+    lib.xrt_simulate_noalloc.argtypes = lib.xrt_simulate.argtypes
     lib.xrt_simulate_rois.argtypes = [C.POINTER(Detector), C.POINTER(Beam), C.POINTER(Crystal), C.c_void_p,
                                       C.c_int32, C.c_int64, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                       C.c_int32, C.c_void_p]
@@ -260,6 +261,22 @@ def simulate(shot, fhkl: Fhkl, precision="fp64", out=None, out_dtype=None, accum
     _check(load().xrt_simulate(C.byref(st.det), C.byref(st.beam), C.byref(st.xtal), fhkl.handle,
                                _PREC[precision], C.c_void_p(out.data_ptr()), dt, int(bool(accumulate)),
                                _stream(stream)))
+    return out
+
+
+def simulate_noalloc(shot, fhkl: Fhkl, out, precision="fp64", accumulate=False, stream=None, roi=None):
+    """Enqueue xrt_simulate_noalloc (xrt_simulate without any device
+    allocation: the library's static scratch array) into the caller's
+    ``out`` tensor; returns ``out``.  Calls that overlap on one device race
+    on that array."""
+    import torch
+    st = ShotStructs(shot, roi)
+    if tuple(out.shape) != st.roi_shape or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError(f"out must be a contiguous GPU tensor of shape {st.roi_shape}")
+    dt = {torch.float32: XRT_F32, torch.float64: XRT_F64}[out.dtype]
+    _check(load().xrt_simulate_noalloc(C.byref(st.det), C.byref(st.beam), C.byref(st.xtal), fhkl.handle,
+                                       _PREC[precision], C.c_void_p(out.data_ptr()), dt, int(bool(accumulate)),
+                                       _stream(stream)))
     return out
 
 
