@@ -416,7 +416,8 @@ def serving_bench(n_pool=1000, n_cap=200, n_fp64=60, loads=(0.5, 0.8, 0.95)):
     give the capacity; then all n_pool arrive as a Poisson stream at each
     load x capacity (a seeded order per load).  Latency is submit -> result
     ready on the server's clock; slowdown is latency over the shot's
-    standalone time.  Also: the capacity of a binary64 server against the
+    standalone time; the offered rate of a load is load x the capacity in
+    terms/s over the pool's mean terms per shot.  Also: the capacity of a binary64 server against the
     binary64 standalone calls of the same shots, and the mixed capacity with
     the water-like background added to every image."""
     import synth
@@ -451,14 +452,20 @@ def serving_bench(n_pool=1000, n_cap=200, n_fp64=60, loads=(0.5, 0.8, 0.95)):
     out["closed_loop"] = closed
     log(f"serving: capacity {closed['images_per_s']:.2f} img/s, {closed['Gterm_per_s']:.0f} Gterm/s, "
         f"{closed['vs_standalone']:.3f} of the standalone calls")
+    # offered load in work: shots of the whole pool arrive at `load` times
+    # the capacity in terms/s over the pool's mean shot (the 200-shot subset's
+    # image rate would misstate it, its mean shot differing from the pool's)
+    mean_terms = float(terms.mean())
+    out["pool"]["mean_terms"] = mean_terms
     for load in loads:
         order = np.random.default_rng(int(round(load * 100))).permutation(n_pool)
         shots = [pool[i] for i in order]
-        rate = load * closed["images_per_s"]
+        rate = load * closed["Gterm_per_s"] * 1e9 / mean_terms
         arr = serve.poisson_arrivals(np.random.default_rng(int(round(load * 1000))), n_pool, rate)
         res = serve.run_stream(srv, shots, arr, on_done=progress(f"load {load:.2f}", n_pool), timeout=900.0)
         st = latency_stats(res, shots, t_mixed[order], rate)
         st["load"] = load
+        st["offered_Gterm_per_s"] = rate * mean_terms / 1e9
         out[f"poisson_{load:.2f}"] = st
         log(f"serving at {load:.2f} x capacity: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms, "
             f"slowdown p50 {st['p50_slowdown']:.2f} p99 {st['p99_slowdown']:.2f}, {st['Gterm_per_s']:.0f} Gterm/s")
