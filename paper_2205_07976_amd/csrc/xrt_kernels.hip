@@ -249,17 +249,29 @@ __device__ __forceinline__ double gauss_exponent(const Params &p, const double h
 // more than e^87 below the reference.  Terms with F^2 = 0 never move m (their
 // exponent is clamped to the step, so 0 * exp stays 0).  The value of the
 // sum is exp(m) (s - c), formed in binary64 by the binary64 term's exp.
+//
+// A raise is rare (the first term with a nonzero F^2, then a few more), so
+// the loops over the terms test for it with one comparison against the
+// threshold mt = m + GAUSS_REF_STEP and leave their inner loop when some lane
+// of the wave needs it (a wave-uniform exit); the raise, with its exponential,
+// is made outside the inner loop and the loop resumes.  Each lane does the
+// same operations in the same order as if the test were made term by term.
 constexpr float GAUSS_REF_STEP = 8.0f;
 
-__device__ __forceinline__ float gauss_rescale(double &m, double e, float F2)
-{
-    float k = 1.0f;
-    if (F2 > 0.0f && e > m + (double)GAUSS_REF_STEP) {
-        k = __expf((float)(m - e));  // 0 for the first such term (m = -inf)
+struct GaussRef {
+    double m = -__builtin_inf();
+    double mt = -__builtin_inf();  // m + GAUSS_REF_STEP
+    __device__ __forceinline__ bool needs_raise(double e, float F2) const { return F2 > 0.0f && e > mt; }
+    // m := e; returns the factor exp(m_old - e) of the sums so far (0 for
+    // the first raise, from m_old = -inf)
+    __device__ __forceinline__ float raise(double e)
+    {
+        const float k = __expf((float)(m - e));
         m = e;
+        mt = e + (double)GAUSS_REF_STEP;
+        return k;
     }
-    return k;
-}
+};
 
 __device__ __forceinline__ void kahan_add(float &s, float &c, float x)
 {
@@ -309,7 +321,7 @@ template <int PREC, int SHAPE, bool CLAMP>
 struct RotSum {
     double s64 = 0.0;
     float s = 0.0f, c = 0.0f;
-    double m = -__builtin_inf();  // mixed Gaussian: reference exponent
+    GaussRef ref;  // mixed Gaussian: reference exponent
     // h = M S by the sequence of this precision
     static __device__ __forceinline__ void hkl(const double M[9], const double S[3], double h[3])
     {
@@ -332,14 +344,30 @@ struct RotSum {
         } else if constexpr (SHAPE == XRT_SHAPE_SINCG) {
             kahan_add(s, c, term_mixed_sincg<CLAMP>(p, tab, h));
         } else {
-            double hr[3], f[3];
-            const double e = gauss_exponent(p, h, hr, f);
-            const float F2 = load_f32(tab, table_offset<CLAMP>(p, hr, p.off32));
-            const float k = gauss_rescale(m, e, F2);
-            s *= k;
-            c *= k;
-            kahan_add(s, c, F2 * __expf(__builtin_fminf((float)(e - m), GAUSS_REF_STEP)));
+            double e;
+            float F2;
+            gauss_term(p, tab, h, e, F2);
+            if (ref.needs_raise(e, F2)) rescale(ref.raise(e));
+            add_gauss(e, F2);
         }
+    }
+    // Mixed Gaussian: the exponent and F^2 of the term at h; the sums scaled
+    // by k; the term F^2 exp(e - m) added.
+    static __device__ __forceinline__ void gauss_term(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3],
+                                                      double &e, float &F2)
+    {
+        double hr[3], f[3];
+        e = gauss_exponent(p, h, hr, f);
+        F2 = load_f32(tab, table_offset<CLAMP>(p, hr, p.off32));
+    }
+    __device__ __forceinline__ void rescale(float k)
+    {
+        s *= k;
+        c *= k;
+    }
+    __device__ __forceinline__ void add_gauss(double e, float F2)
+    {
+        kahan_add(s, c, F2 * __expf(__builtin_fminf((float)(e - ref.m), GAUSS_REF_STEP)));
     }
     // The sum in binary64 (mixed Gaussian: exp(m) (s - c)).
     __device__ __forceinline__ double value() const
@@ -349,7 +377,7 @@ struct RotSum {
         else if constexpr (SHAPE == XRT_SHAPE_SINCG)
             return (double)(s - c);
         else
-            return exp_f64(m) * (double)(s - c);
+            return exp_f64(ref.m) * (double)(s - c);
     }
 };
 
@@ -369,6 +397,37 @@ __device__ __forceinline__ void rot_sum(const Params &p, __amdgpu_buffer_rsrc_t 
                                         const double S[3], RotSum<PREC, SHAPE, CLAMP> &acc)
 {
     const int n = p.n_rot;
+    if constexpr (PREC == XRT_MIXED && SHAPE == XRT_SHAPE_GAUSS) {
+        // the inner loop runs until some lane must raise its reference
+        // exponent at term r (wave-uniform exit); the raise and term r are
+        // done outside it
+        double m[9];
+        if (PF) load9(m, mats);
+        int r = 0;
+        while (r < n) {
+            double e = 0.0;
+            float F2 = 0.0f;
+            bool need = false;
+            for (; r < n; ++r) {
+                double h[3];
+                if (PF) {
+                    acc.hkl(m, S, h);
+                    load9(m, mats + 9 * (r + 1 < n ? r + 1 : r));
+                } else {
+                    acc.hkl(mats + 9 * r, S, h);
+                }
+                acc.gauss_term(p, tab, h, e, F2);
+                need = acc.ref.needs_raise(e, F2);
+                if (__builtin_amdgcn_ballot_w64(need)) break;
+                acc.add_gauss(e, F2);
+            }
+            if (r == n) break;
+            if (need) acc.rescale(acc.ref.raise(e));
+            acc.add_gauss(e, F2);
+            ++r;
+        }
+        return;
+    }
     if (PF) {
         double m[9];
         load9(m, mats);
@@ -1095,41 +1154,77 @@ __device__ __forceinline__ void grad_term_f64(const Params &p, __amdgpu_buffer_r
 // derivatives and the products in binary32, as terms F^2 exp(e - m) against
 // the reference exponent m of the forward's mixed Gaussian sums (the 13
 // binary32 sums of one (sample point, source) are rescaled with m and added
-// into binary64 as exp(m) times their value).
+// into binary64 as exp(m) times their value).  grad_prep_mixed forms what a
+// term needs up to its exponent and F^2, grad_add_mixed adds it; the term loop
+// raises the reference between the two, as the forward's does.
+struct GradTerm {
+    float f[3], Sf[3];
+    double e;
+    float F2;
+};
+
 template <bool CLAMP>
-__device__ __forceinline__ void grad_term_mixed(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *Q,
-                                                const double S[3], float w, float acc[13], double &m)
+__device__ __forceinline__ void grad_prep_mixed(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *Q,
+                                                const double S[3], GradTerm &g)
 {
     double Sp[3], hr[3], fd[3];
-    float f[3], Sf[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         Sp[c] = __builtin_fma(Q[6 + c], S[2], __builtin_fma(Q[3 + c], S[1], Q[c] * S[0]));
-        Sf[c] = (float)Sp[c];
+        g.Sf[c] = (float)Sp[c];
     }
     double h[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
         h[i] = __builtin_fma(p.m0[3 * i + 2], Sp[2], __builtin_fma(p.m0[3 * i + 1], Sp[1], p.m0[3 * i] * Sp[0]));
-    const double e = gauss_exponent(p, h, hr, fd);
+    g.e = gauss_exponent(p, h, hr, fd);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) f[i] = (float)fd[i];
-    const float F2 = load_f32(tab, table_offset<CLAMP>(p, hr, p.off32));
-    const float k = gauss_rescale(m, e, F2);
-    if (k != 1.0f) {
-#pragma unroll
-        for (int c = 0; c < 13; ++c) acc[c] *= k;
-    }
-    const float base = w * F2 * __expf(__builtin_fminf((float)(e - m), GAUSS_REF_STEP));
+    for (int i = 0; i < 3; ++i) g.f[i] = (float)fd[i];
+    g.F2 = load_f32(tab, table_offset<CLAMP>(p, hr, p.off32));
+}
+
+__device__ __forceinline__ void grad_add_mixed(const Params &p, const GradTerm &g, float w, float acc[13],
+                                               const GaussRef &ref)
+{
+    const float base = w * g.F2 * __expf(__builtin_fminf((float)(g.e - ref.m), GAUSS_REF_STEP));
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        const float dh = base * (float)p.m2gk[i] * f[i];
+        const float dh = base * (float)p.m2gk[i] * g.f[i];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[3 * i + c] = __builtin_fmaf(dh, Sf[c], acc[3 * i + c]);
-        acc[9 + i] = __builtin_fmaf(base * (float)p.inv2N[i], __builtin_fmaf(-(float)p.gk[i], f[i] * f[i], 1.0f),
-                                    acc[9 + i]);
+        for (int c = 0; c < 3; ++c) acc[3 * i + c] = __builtin_fmaf(dh, g.Sf[c], acc[3 * i + c]);
+        acc[9 + i] = __builtin_fmaf(base * (float)p.inv2N[i],
+                                    __builtin_fmaf(-(float)p.gk[i], g.f[i] * g.f[i], 1.0f), acc[9 + i]);
     }
     acc[12] += base;
+}
+
+// The 13 binary32 sums of one (sample point, source) over its n_rot terms,
+// leaving the inner loop only when some lane must raise its reference
+// exponent (as rot_sum does for the forward sums).
+template <bool CLAMP>
+__device__ __forceinline__ void grad_rot_mixed(const Params &p, __amdgpu_buffer_rsrc_t tab, const double S[3], float w,
+                                               float acc[13], GaussRef &ref)
+{
+    const int n = p.n_rot;
+    int r = 0;
+    while (r < n) {
+        GradTerm g;
+        bool need = false;
+        for (; r < n; ++r) {
+            grad_prep_mixed<CLAMP>(p, tab, p.qmats + 9 * r, S, g);
+            need = ref.needs_raise(g.e, g.F2);
+            if (__builtin_amdgcn_ballot_w64(need)) break;
+            grad_add_mixed(p, g, w, acc, ref);
+        }
+        if (r == n) break;
+        if (need) {
+            const float k = ref.raise(g.e);
+#pragma unroll
+            for (int c = 0; c < 13; ++c) acc[c] *= k;
+        }
+        grad_add_mixed(p, g, w, acc, ref);
+        ++r;
+    }
 }
 
 // Sum of v over the 256 lanes of a workgroup by a fixed tree: xor-shuffles
@@ -1175,10 +1270,9 @@ __global__ __launch_bounds__(BLOCK) void grad_kernel(const Params p, const void 
                         float a32[13];
 #pragma unroll
                         for (int c = 0; c < 13; ++c) a32[c] = 0.0f;
-                        double m = -__builtin_inf();
-                        for (int r = 0; r < p.n_rot; ++r)
-                            grad_term_mixed<CLAMP>(p, tab, p.qmats + 9 * r, S, (float)w, a32, m);
-                        const double em = exp_f64(m);
+                        GaussRef ref;
+                        grad_rot_mixed<CLAMP>(p, tab, S, (float)w, a32, ref);
+                        const double em = exp_f64(ref.m);
 #pragma unroll
                         for (int c = 0; c < 13; ++c) acc[c] = __builtin_fma(em, (double)a32[c], acc[c]);
                     }
