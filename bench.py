@@ -363,6 +363,23 @@ def adjoint_bench(steps):
                      "loss": float(((img - target) ** 2).sum())}
         log(f"adjoint {prec}: forward {fms:.1f} ms (frac {out[prec]['fwd_roofline']['frac']:.3f}), "
             f"backward {bms:.1f} ms (frac {out[prec]['bwd_roofline']['frac']:.3f})")
+    # the oracle's binary64 gradient on a seeded sample of the regions'
+    # pixels (dL/dI of the binary64 residual), on every host thread
+    from oracle import oracle as o
+    rng = np.random.default_rng(55)
+    pick = rng.choice(len(origins) * size[0] * size[1], 1024, replace=False)
+    q, rem = np.divmod(pick, size[0] * size[1])
+    ls, lf = np.divmod(rem, size[0])  # [n_roi][ns][nf], size = (nf, ns)
+    pix = np.stack([origins[q, 0] + lf, origins[q, 1] + ls], axis=1).astype(np.int32)
+    img64 = xrt.simulate_rois(base, fh, origins, size, precision="fp64", out_dtype=torch.float64)
+    res = (2 * (img64 - target)).cpu().numpy().reshape(-1)[pick]
+    cores = host_threads()
+    t0 = time.perf_counter()
+    o.gradient(base, pix, res, nthreads=cores)
+    dt = time.perf_counter() - t0
+    out["cpu_oracle_gradient"] = {"Gterm_s": len(pix) * shot.terms_per_pixel / dt / 1e9, "cores": cores,
+                                  "sample": f"{len(pix)} seeded pixels of the 512 regions ({dt:.2f} s)"}
+    log(f"adjoint: oracle gradient {out['cpu_oracle_gradient']}")
     d = np.abs(grads["mixed"] - grads["fp64"])
     out["grad_fp64"] = grads["fp64"].tolist()
     out["mixed_vs_fp64_max_diff_over_max"] = [float(d[sl].max() / np.abs(grads["fp64"][sl]).max())
@@ -418,8 +435,9 @@ def serving_bench(n_pool=1000, n_cap=200, n_fp64=60, loads=(0.5, 0.8, 0.95)):
     ready on the server's clock; slowdown is latency over the shot's
     standalone time; the offered rate of a load is load x the capacity in
     terms/s over the pool's mean terms per shot.  Also: the capacity of a binary64 server against the
-    binary64 standalone calls of the same shots, and the mixed capacity with
-    the water-like background added to every image."""
+    binary64 standalone calls of the same shots, the capacity again under a
+    256 MiB HBM budget, and the mixed capacity with the water-like background
+    added to every image."""
     import synth
     from paper_2205_07976_amd import serve, xrt
     base = synth.full_shot()
@@ -470,6 +488,15 @@ def serving_bench(n_pool=1000, n_cap=200, n_fp64=60, loads=(0.5, 0.8, 0.95)):
         log(f"serving at {load:.2f} x capacity: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms, "
             f"slowdown p50 {st['p50_slowdown']:.2f} p99 {st['p99_slowdown']:.2f}, {st['Gterm_per_s']:.0f} Gterm/s")
     srv.close()
+    # admission under a small HBM budget: the capacity run again with 256 MiB
+    # (fewer shots resident at once; the largest image is 25 MB)
+    srv = xrt.Server(fh, hbm_budget=256 << 20, max_resident=64, precision="mixed")
+    serve.run_stream(srv, pool[:2], np.zeros(2))
+    small = serve.summarize(serve.run_stream(srv, cap, np.zeros(n_cap)), cap)
+    srv.close()
+    small["vs_standalone"] = closed["standalone_s"] / small["makespan_s"]
+    out["closed_loop_256MiB"] = small
+    log(f"serving under a 256 MiB budget: {small['images_per_s']:.2f} img/s ({small['vs_standalone']:.3f})")
     # binary64: served capacity against standalone binary64 calls
     sub = pool[:n_fp64]
     t64 = standalone_times(sub, fh, "fp64", "fp64")
