@@ -115,6 +115,56 @@ def profile_keys(name):
     return None
 
 
+def read_sclk_mhz():
+    """The shader clock of the first GPU that reports one, MHz (the active
+    level of pp_dpm_sclk in sysfs), or None where sysfs does not expose it."""
+    import glob
+    import re
+    for f in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")):
+        try:
+            with open(f) as fp:
+                for line in fp:
+                    if "*" in line:
+                        m = re.search(r"(\d+)\s*Mhz", line, re.I)
+                        if m:
+                            return float(m.group(1))
+        except OSError:
+            continue
+    return None
+
+
+class SclkSampler:
+    """Samples read_sclk_mhz() every period_s in a thread while the timed
+    region runs (a sysfs read: no GPU work)."""
+
+    def __init__(self, period_s=0.05):
+        import threading
+        self.samples, self.period, self._stop = [], period_s, threading.Event()
+        self._t = threading.Thread(target=self._run, daemon=True)
+
+    def _run(self):
+        while not self._stop.is_set():
+            v = read_sclk_mhz()
+            if v is not None:
+                self.samples.append(v)
+            self._stop.wait(self.period)
+
+    def __enter__(self):
+        self._t.start()
+        return self
+
+    def __exit__(self, *exc):
+        self._stop.set()
+        self._t.join()
+
+    def summary(self):
+        if not self.samples:
+            return {"mhz_median": None, "note": "sysfs pp_dpm_sclk not readable on this host"}
+        v = np.array(self.samples)
+        return {"mhz_median": float(np.median(v)), "mhz_min": float(v.min()), "mhz_max": float(v.max()),
+                "samples": len(v)}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -632,7 +682,8 @@ def main():
     terms = shot.n_terms
     log(f"full-size shot: {terms:.4e} terms; fp64 warmup {args.warmup} steps {args.steps}")
 
-    img64, wall, ev = time_form(shot, fh, "fp64", args.steps, args.warmup)
+    with SclkSampler() as sclk:
+        img64, wall, ev = time_form(shot, fh, "fp64", args.steps, args.warmup)
     ms = 1e3 * wall / args.steps
     kern_ms = sum(ev) / len(ev)
     value = terms / (wall / args.steps) / 1e9
@@ -652,7 +703,8 @@ def main():
                      "flop_per_term": rf["flop_per_term"],
                      "counters": ctr["fp64"] if ctr else None,
                      "counters_source": ctr["source"] if ctr else None,
-                     "issue_efficiency": ISSUE_SLOTS["fp64"] * terms / (kern_ms * 1e-3) / ISSUE_PEAK},
+                     "issue_efficiency": ISSUE_SLOTS["fp64"] * terms / (kern_ms * 1e-3) / ISSUE_PEAK,
+                     "sclk_during_timed_region": sclk.summary()},
     }
     log(f"fp64: {ms:.1f} ms/step (events {kern_ms:.1f} ms), {value:.1f} Gterm/s, "
         f"{rf['achieved']:.1f} algorithmic TFLOP/s, roofline frac {rf['frac']:.3f}")

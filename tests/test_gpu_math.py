@@ -2,8 +2,9 @@
 lattice factor uses for sin(pi f) and sin(pi g), paper section II's
 crystal-size transform), against references that share nothing with it:
 
-* binary64 form: 2^22 seeded points and edge points of [-1/2, 1/2] against
-  sin computed on the host in 80-bit extended precision; odd symmetry exact;
+* binary64 form: 6 x 2^24 seeded points and edge points of [0, 1/2] (about
+  10^8) against sin computed on the host in 80-bit extended precision;
+  odd symmetry exact;
 * binary32 form: every normal binary32 value in [2^-126, 1/2] against the
   GPU's binary64 sin.  Subnormal inputs are left out: whether the device
   flushes them is a compiler mode, and the lattice factor never depends on
