@@ -475,7 +475,7 @@ def latency_stats(res, shots, t_alone, offered_rate=None):
     return out
 
 
-def serving_bench(n_pool=1000, n_cap=200, n_fp64=60, loads=(0.5, 0.8, 0.95)):
+def serving_bench(n_pool=1000, n_cap=200, n_fp64=60, loads=(0.5, 0.8, 0.95), policy="shortest_remaining"):
     """The served shot stream (independent shots: random orientation,
     log-uniform ROI 64..2463 x 64..2527 px, 1-100 sources, 1-200 domains,
     N in [5, 40], the full-size detector and shared table).  A pool of n_pool
@@ -507,10 +507,11 @@ def serving_bench(n_pool=1000, n_cap=200, n_fp64=60, loads=(0.5, 0.8, 0.95)):
 
     out = {"workload": "served stream: log-uniform ROI, 1-100 sources, 1-200 domains, N in [5,40], "
                        "full-size detector and table, mixed",
+           "policy": policy,
            "pool": {"shots": n_pool, "terms": float(terms.sum()),
                     "standalone_mixed_s": float(t_mixed.sum()),
                     "standalone_mixed_Gterm_s": float(terms.sum() / t_mixed.sum() / 1e9)}}
-    srv = xrt.Server(fh, hbm_budget=16 << 30, max_resident=64, precision="mixed")
+    srv = xrt.Server(fh, hbm_budget=16 << 30, max_resident=64, precision="mixed", policy=policy)
     serve.run_stream(srv, pool[:2], np.zeros(2))  # the persistent kernel's first launch
     cap = pool[:n_cap]
     res = serve.run_stream(srv, cap, np.zeros(n_cap), on_done=progress("capacity", n_cap))
@@ -540,7 +541,7 @@ def serving_bench(n_pool=1000, n_cap=200, n_fp64=60, loads=(0.5, 0.8, 0.95)):
     srv.close()
     # admission under a small HBM budget: the capacity run again with 256 MiB
     # (fewer shots resident at once; the largest image is 25 MB)
-    srv = xrt.Server(fh, hbm_budget=256 << 20, max_resident=64, precision="mixed")
+    srv = xrt.Server(fh, hbm_budget=256 << 20, max_resident=64, precision="mixed", policy=policy)
     serve.run_stream(srv, pool[:2], np.zeros(2))
     small = serve.summarize(serve.run_stream(srv, cap, np.zeros(n_cap)), cap)
     srv.close()
@@ -550,7 +551,7 @@ def serving_bench(n_pool=1000, n_cap=200, n_fp64=60, loads=(0.5, 0.8, 0.95)):
     # binary64: served capacity against standalone binary64 calls
     sub = pool[:n_fp64]
     t64 = standalone_times(sub, fh, "fp64", "fp64")
-    srv = xrt.Server(fh, hbm_budget=16 << 30, max_resident=64, precision="fp64")
+    srv = xrt.Server(fh, hbm_budget=16 << 30, max_resident=64, precision="fp64", policy=policy)
     serve.run_stream(srv, sub[:2], np.zeros(2))
     c64 = serve.summarize(serve.run_stream(srv, sub, np.zeros(n_fp64)), sub)
     srv.close()
@@ -562,7 +563,7 @@ def serving_bench(n_pool=1000, n_cap=200, n_fp64=60, loads=(0.5, 0.8, 0.95)):
         f"({c64['vs_standalone']:.3f})")
     # the mixed closed loop with the water-like background on every image
     srv = xrt.Server(fh, hbm_budget=16 << 30, max_resident=64, precision="mixed",
-                     background=synth.water_background())
+                     background=synth.water_background(), policy=policy)
     serve.run_stream(srv, sub[:2], np.zeros(2))
     out["closed_loop_with_background"] = serve.summarize(serve.run_stream(srv, sub, np.zeros(n_fp64)), sub)
     srv.close()
@@ -658,6 +659,8 @@ def main():
     ap.add_argument("--only", default="",
                     help="comma-separated sections to run after the binary64 full shot (default: "
                          + ",".join(DEFAULT_SECTIONS) + "; also available: serving_io)")
+    ap.add_argument("--serve-policy", default="shortest_remaining", choices=("shortest_remaining", "fair_share"),
+                    help="publication order of the served stream's chunks")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="finish with one device-to-device copy of this many MiB (a kernel of known "
                          "traffic that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -749,7 +752,7 @@ def main():
         res["served_region"] = served_region_bench(args.steps)
         res["served_region"]["counters"] = profile_keys("serve_region_counters.txt")
     if "serving" in sections:
-        res["serving"] = serving_bench()
+        res["serving"] = serving_bench(policy=args.serve_policy)
         res["p50_shot_latency_ms"] = res["serving"]["poisson_0.80"]["p50_ms"]
         res["p99_shot_latency_ms"] = res["serving"]["poisson_0.80"]["p99_ms"]
     if "serving_io" in sections:

@@ -322,9 +322,9 @@ xrt_status xrt_add_images(double *dev_acc, int32_t acc_nf, int32_t acc_ns,
  * factors (shared by every shot); shot descriptors and tables sit in pinned
  * host memory that the kernel reads directly.  Submitted shots wait in
  * arrival order; a shot is admitted when its footprint fits in the arena and
- * a resident slot is free; the work of admitted shots is fed in chunks, the
- * shot with the least work published so far first, to a persistent kernel
- * that keeps running while new shots join.  Every pixel is computed exactly
+ * a resident slot is free; the work of admitted shots is fed in chunks, in
+ * the order of the server's policy (below), to a persistent kernel that keeps
+ * running while new shots join.  Every pixel is computed exactly
  * as by xrt_simulate with the server's precision (the same summation order),
  * so a shot's image is bit-identical whatever else runs beside it.
  * Calls on one server are serialised internally; progress is driven by
@@ -368,9 +368,22 @@ typedef struct xrt_server_desc {
                                complete (the image of xrt_simulate followed by
                                xrt_simulate_background with accumulate, bit
                                for bit); read during xrt_server_create only */
+    int32_t policy;         /* XRT_SERVE_FAIR_SHARE or XRT_SERVE_SHORTEST_REMAINING */
 } xrt_server_desc;
 
 enum { XRT_SHOT_QUEUED = 0, XRT_SHOT_RUNNING = 1, XRT_SHOT_DONE = 2 };
+
+/* Order in which the work of admitted shots goes to the device.
+ * XRT_SERVE_FAIR_SHARE: the next chunk comes from the shot with the least
+ *   work (pixel-terms) published so far, a shot admitted later joining at the
+ *   current level: resident shots share the device evenly by work
+ *   (start-time fair queuing).
+ * XRT_SERVE_SHORTEST_REMAINING: the next chunk comes from the shot with the
+ *   least work left to publish (shortest remaining processing time): a small
+ *   shot overtakes the large ones in flight, which minimises mean latency and
+ *   slowdown; under sustained overload the largest shots wait longest.
+ * Admission stays in arrival order either way. */
+enum { XRT_SERVE_FAIR_SHARE = 0, XRT_SERVE_SHORTEST_REMAINING = 1 };
 
 typedef struct xrt_shot_info {
     uint32_t struct_size;

@@ -24,6 +24,7 @@ constexpr int TILE_PIXELS = 256;            // 16 x 16 pixels per tile
 constexpr uint64_t CHUNK_TERMS = 1u << 20;  // pixel-terms a compute chunk aims at
 constexpr int MAX_CHUNK = 64;               // work units per chunk
 enum { PHASE_COMPUTE = 0, PHASE_REDUCE = 1, PHASE_BACKGROUND = 2 };
+enum { POLICY_FAIR_SHARE = 0, POLICY_SHORTEST_REMAINING = 1 };
 enum { QUEUED = 0, RUNNING = 1, DONE = 2 };
 
 inline uint64_t align_up(uint64_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
@@ -90,7 +91,9 @@ struct Work {
     int32_t phase = PHASE_COMPUTE;
     int32_t n_units = 0, chunk_units = 1, next_unit = 0;
     int64_t chunks_total = 0, chunks_done = 0;
-    double work_published = 0;     // pixel-terms of the chunks published so far
+    double work_published = 0;     // fair share: the shot's level (its start level plus
+                                   // the pixel-terms of its chunks published since)
+    double work_left = 0;          // pixel-terms of every phase not yet published
 };
 
 // One published chunk: units [unit0, unit0 + n_units) of a shot's phase.
@@ -106,9 +109,11 @@ class Scheduler {
     // dev_bytes / host_bytes: arena sizes; n_wg: workgroups of the persistent
     // kernel (chunk sizing and the publication depth); ring: capacity of the
     // ring of chunk records.
-    Scheduler(uint64_t dev_bytes, uint64_t host_bytes, int max_resident, int n_wg, uint32_t ring)
+    Scheduler(uint64_t dev_bytes, uint64_t host_bytes, int max_resident, int n_wg, uint32_t ring,
+              int policy = POLICY_FAIR_SHARE)
         : dev_(dev_bytes), host_(host_bytes), max_resident_(max_resident), n_wg_(std::max(n_wg, 1)),
-          depth_(std::min<size_t>(ring - 1, 2 * (size_t)std::max(n_wg, 1))), ring_(ring)
+          depth_(std::min<size_t>(ring - 1, 2 * (size_t)std::max(n_wg, 1))), ring_(ring),
+          slack_(2.0 * (double)std::max(n_wg, 1) * (double)CHUNK_TERMS), policy_(policy)
     {
     }
 
@@ -147,6 +152,9 @@ class Scheduler {
             w.state = RUNNING;
             start_phase(w, PHASE_COMPUTE);
             w.work_published = vtime_;  // it competes from now on, not from the start
+            w.work_left = (double)w.n_tiles * TILE_PIXELS *
+                          ((double)w.terms_per_pixel + (w.split > 1 ? (double)w.split : 0.0) +
+                           (double)w.bg_terms_per_pixel);
             resident_++;
             admitted_.push_back(w.ticket);
             queue_.pop_front();
@@ -154,28 +162,40 @@ class Scheduler {
         return 0;
     }
 
-    // Publication while fewer than `depth` chunks are in flight and the new
+    // Publication while fewer than `depth` chunks are in flight, the new
     // sequence number stays within `ring` of the oldest chunk still in flight
     // (records and done flags live at seq % ring: a slow chunk must not share
-    // its slot with a later one): the next chunk always comes from the
-    // admitted shot with the least work published so far (pixel-terms; ties
-    // to the earlier ticket), so resident shots share the device evenly by
-    // work whatever their chunk sizes, and a shot admitted later joins at the
-    // current level.  emit(const Chunk &, Work &) writes the record.  Returns
-    // the number of chunks published.
+    // its slot with a later one), and the chunks waiting for a workgroup hold
+    // less than `slack` pixel-terms (about two standard chunks per workgroup:
+    // enough that no workgroup waits for the host between two progress calls,
+    // few enough that a shot admitted now is not queued behind a full round
+    // of another shot's tile-sized chunks, which reach 6e7 terms, ~0.1 s of a
+    // workgroup).  Workgroups claim chunks in publication order, so the
+    // waiting ones are taken to be the in-flight chunks after the oldest
+    // n_wg.  The next chunk comes, under POLICY_FAIR_SHARE, from the
+    // admitted shot with the least work published so far (pixel-terms), so
+    // resident shots share the device evenly by work whatever their chunk
+    // sizes and a shot admitted later joins at the current level; under
+    // POLICY_SHORTEST_REMAINING, from the admitted shot with the least work
+    // left to publish, so a small shot overtakes the large ones in flight.
+    // Ties go to the earlier ticket.  emit(const Chunk &, Work &) writes the
+    // record.  Returns the number of chunks published.
     template <class Emit>
     size_t publish(Emit emit)
     {
         size_t n = 0;
         // inflight_ is in publication order: its front is the oldest chunk
+        double waiting = 0;
+        for (size_t i = (size_t)n_wg_; i < inflight_.size(); ++i) waiting += inflight_[i].work;
         while (inflight_.size() < depth_ && !admitted_.empty() &&
-               (inflight_.empty() || tail_ - inflight_.front().seq < ring_)) {
+               (inflight_.empty() || tail_ - inflight_.front().seq < ring_) &&
+               (inflight_.size() < (size_t)n_wg_ || waiting < slack_)) {
             size_t best = 0;
             for (size_t i = 1; i < admitted_.size(); ++i) {
                 const Work &a = work_[admitted_[i]], &b = work_[admitted_[best]];
-                if (a.work_published < b.work_published ||
-                    (a.work_published == b.work_published && a.ticket < b.ticket))
-                    best = i;
+                const double ka = policy_ == POLICY_SHORTEST_REMAINING ? a.work_left : a.work_published;
+                const double kb = policy_ == POLICY_SHORTEST_REMAINING ? b.work_left : b.work_published;
+                if (ka < kb || (ka == kb && a.ticket < b.ticket)) best = i;
             }
             Work &w = work_[admitted_[best]];
             vtime_ = w.work_published;
@@ -187,11 +207,14 @@ class Scheduler {
             c.n_units = std::min(w.chunk_units, w.n_units - w.next_unit);
             w.next_unit += c.n_units;
             // a reduce chunk reads K values per pixel: count it as K terms
-            w.work_published += (double)c.n_units * TILE_PIXELS *
-                                (w.phase == PHASE_COMPUTE  ? (double)w.terms_per_pixel / w.split
-                                 : w.phase == PHASE_REDUCE ? (double)w.split
-                                                           : (double)w.bg_terms_per_pixel);
-            inflight_.push_back({c.seq, c.ticket});
+            const double cw = (double)c.n_units * TILE_PIXELS *
+                              (w.phase == PHASE_COMPUTE  ? (double)w.terms_per_pixel / w.split
+                               : w.phase == PHASE_REDUCE ? (double)w.split
+                                                         : (double)w.bg_terms_per_pixel);
+            w.work_published += cw;
+            w.work_left -= cw;
+            inflight_.push_back({c.seq, c.ticket, cw});
+            if (inflight_.size() > (size_t)n_wg_) waiting += cw;
             emit(c, w);
             ++n;
             if (w.next_unit >= w.n_units) admitted_.erase(admitted_.begin() + best);
@@ -262,6 +285,15 @@ class Scheduler {
     }
     size_t in_flight() const { return inflight_.size(); }
     size_t depth() const { return depth_; }
+    int policy() const { return policy_; }
+    double slack() const { return slack_; }
+    // pixel-terms of the in-flight chunks after the oldest n_wg
+    double waiting_work() const
+    {
+        double x = 0;
+        for (size_t i = (size_t)n_wg_; i < inflight_.size(); ++i) x += inflight_[i].work;
+        return x;
+    }
     uint64_t resident() const { return resident_; }
     uint64_t published() const { return tail_; }
     const Arena &dev_arena() const { return dev_; }
@@ -270,6 +302,7 @@ class Scheduler {
   private:
     struct InFlight {
         uint64_t seq, ticket;
+        double work;  // pixel-terms
     };
 
     // Chunking of a phase: compute and background chunks hold about
@@ -300,6 +333,8 @@ class Scheduler {
     int n_wg_;
     size_t depth_;
     uint64_t ring_;
+    double slack_;  // pixel-terms allowed in chunks that wait for a workgroup
+    int policy_;
     uint64_t resident_ = 0, tail_ = 0;
     double vtime_ = 0;  // published work of the shot served last
     std::deque<uint64_t> queue_;         // submitted, not admitted (FIFO)

@@ -139,6 +139,8 @@ xrt_status check_desc(const xrt_server_desc *d)
     if (!(d->idle_exit_us >= 1.0 && d->idle_exit_us <= 1e6)) return fail(XRT_ERANGE, "idle_exit_us must be in [1, 1e6]");
     if (d->host_budget != 0 && (d->host_budget < (1u << 20) || d->host_budget > ((uint64_t)1 << 40)))
         return fail(XRT_ERANGE, "host_budget must be 0 or in [1 MiB, 1 TiB]");
+    if (d->policy != XRT_SERVE_FAIR_SHARE && d->policy != XRT_SERVE_SHORTEST_REMAINING)
+        return fail(XRT_EINVAL, "unknown policy %d", d->policy);
     if (d->background) return xrt::host::check_background_desc(d->background);
     return XRT_OK;
 }
@@ -412,7 +414,10 @@ xrt_status xrt_server_create(const xrt_server_desc *desc, const xrt_fhkl *fhkl, 
     std::memset(s->ctrl, 0, sizeof(xrt::ServeCtrl));
     std::memset(s->ring, 0, sizeof(xrt::ServeChunk) * RING);
     std::memset(s->done, 0, sizeof(uint32_t) * RING);
-    s->sched = new (std::nothrow) xrt::sched::Scheduler(desc->hbm_budget, s->host_bytes, desc->max_resident, s->n_wg, RING);
+    s->sched = new (std::nothrow) xrt::sched::Scheduler(
+        desc->hbm_budget, s->host_bytes, desc->max_resident, s->n_wg, RING,
+        desc->policy == XRT_SERVE_SHORTEST_REMAINING ? xrt::sched::POLICY_SHORTEST_REMAINING
+                                                     : xrt::sched::POLICY_FAIR_SHARE);
     if (s->out) s->out_arena = new (std::nothrow) xrt::sched::Arena(desc->host_budget);
     if (!s->sched || (s->out && !s->out_arena)) {
         free_server(s);

@@ -80,7 +80,7 @@ class ServerDesc(C.Structure):
         ("struct_size", C.c_uint32), ("hbm_budget", C.c_uint64), ("max_resident", C.c_int32),
         ("precision", C.c_int32), ("shape", C.c_int32), ("out_dtype", C.c_int32),
         ("workgroups", C.c_int32), ("idle_exit_us", C.c_double), ("host_budget", C.c_uint64),
-        ("background", C.c_void_p),
+        ("background", C.c_void_p), ("policy", C.c_int32),
     ]
 
 
@@ -107,6 +107,8 @@ SYMBOLS = ("xrt_version", "xrt_last_error", "xrt_fhkl_create", "xrt_fhkl_destroy
            "xrt_server_image", "xrt_server_host_image", "xrt_server_release", "xrt_server_cancel", "xrt_cell_mats", "xrt_trace_terms", "xrt_sinpi", "xrt_exp",
            "xrt_simulate_background", "xrt_add_image", "xrt_add_images", "xrt_simulate_noalloc")
 XRT_SHOT_QUEUED, XRT_SHOT_RUNNING, XRT_SHOT_DONE = 0, 1, 2
+XRT_SERVE_FAIR_SHARE, XRT_SERVE_SHORTEST_REMAINING = 0, 1
+_POLICY = {"fair_share": XRT_SERVE_FAIR_SHARE, "shortest_remaining": XRT_SERVE_SHORTEST_REMAINING}
 
 
 def load():
@@ -438,11 +440,13 @@ class Server:
     """xrt_server_*: continuous batching of independent shots on the current
     device (see include/xrt.h).  submit() queues a shot and returns a ticket;
     progress() must be called often; image(ticket) returns a finished image as
-    a torch tensor viewing the server's arena (copy it before release)."""
+    a torch tensor viewing the server's arena (copy it before release).
+    policy: "shortest_remaining" (the next chunk from the shot with the least
+    work left) or "fair_share" (from the shot with the least work published)."""
 
     def __init__(self, fhkl: Fhkl, hbm_budget=8 << 30, max_resident=256, precision="mixed",
                  shape=XRT_SHAPE_SINCG, out_dtype=None, workgroups=0, idle_exit_us=5000.0, host_budget=0,
-                 background=None):
+                 background=None, policy="shortest_remaining"):
         self.fhkl = fhkl  # kept alive: the server borrows its tables
         self.out_f64 = (out_dtype == "f64") if out_dtype else precision == "fp64"
         self.writes_out = bool(host_budget)
@@ -453,7 +457,7 @@ class Server:
                                 float(background.molecules))
         d = ServerDesc(C.sizeof(ServerDesc), int(hbm_budget), int(max_resident), _PREC[precision], int(shape),
                        XRT_F64 if self.out_f64 else XRT_F32, int(workgroups), float(idle_exit_us), int(host_budget),
-                       C.cast(C.pointer(bg), C.c_void_p) if bg is not None else None)
+                       C.cast(C.pointer(bg), C.c_void_p) if bg is not None else None, _POLICY[policy])
         h = C.c_void_p()
         _check(load().xrt_server_create(C.byref(d), fhkl.handle, C.byref(h)))
         self._h = h

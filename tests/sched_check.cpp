@@ -6,6 +6,8 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstdint>
 #include <map>
 #include <random>
 #include <set>
@@ -269,6 +271,97 @@ static void check_fair_share()
     CHECK(n2 * 10 >= n3 * 8 && n3 * 10 >= n2 * 8);  // equal-cost chunks: equal counts, within 20 %
 }
 
+static void check_waiting_bound()
+{
+    printf("publication: chunks waiting for a workgroup hold under the slack; a late shot is not queued behind them\n");
+    const int n_wg = 16;
+    const double big = 256.0 * 200000;  // one tile per chunk: 5.1e7 terms
+    Scheduler s(1 << 30, 1 << 22, 8, n_wg, 1 << 16);
+    Device d(s);
+    CHECK(s.slack() == 2.0 * n_wg * CHUNK_TERMS && s.depth() == 2 * (size_t)n_wg);
+    s.submit(shot(1, 4096, 100000, 200000));
+    s.admit([](Work &) { return 0; });
+    for (int it = 0; it < 50; ++it) {
+        d.publish();
+        // the chunk that crossed the slack is the only one past it
+        CHECK(s.in_flight() <= (size_t)n_wg || s.waiting_work() < s.slack() + big);
+        CHECK(s.in_flight() <= (size_t)n_wg + 1);
+        d.run(3, false);
+        d.collect();
+    }
+    // a small shot admitted now gets the next free workgroup: its first chunk
+    // is published as soon as one of the in-flight chunks finishes
+    d.publish();
+    const size_t mark = d.log.size();
+    s.submit(shot(2, 4096, 64, 100));
+    s.admit([](Work &) { return 0; });
+    d.run(1, false);
+    d.collect();
+    d.publish();
+    bool seen = false;
+    for (size_t i = mark; i < d.log.size(); ++i) seen = seen || d.log[i].ticket == 2;
+    CHECK(seen);
+    // with cheap chunks only, the count bound (depth) is the one that binds
+    Scheduler t(1 << 30, 1 << 22, 8, n_wg, 1 << 16);
+    Device e(t);
+    t.submit(shot(3, 4096, 100000, 10));
+    t.admit([](Work &) { return 0; });
+    e.publish();
+    CHECK(t.in_flight() == t.depth());
+}
+
+static void check_shortest_remaining()
+{
+    printf("publication, shortest remaining: the shot with the least work left goes first; a small late shot overtakes\n");
+    const int n_wg = 8;
+    Scheduler s(1 << 30, 1 << 22, 8, n_wg, 1 << 16, POLICY_SHORTEST_REMAINING);
+    Device d(s);
+    CHECK(s.policy() == POLICY_SHORTEST_REMAINING);
+    s.submit(shot(1, 4096, 2000, 100000));  // large: 5.1e10 terms
+    s.submit(shot(2, 4096, 300, 100000));   // medium
+    s.admit([](Work &) { return 0; });
+    // the medium shot, with less left, takes every chunk until it is all published
+    for (int it = 0; it < 200 && s.find(2)->next_unit < s.find(2)->n_units; ++it) {
+        d.publish();
+        d.run(4, false);
+        d.collect();
+    }
+    uint64_t last2 = 0, first1 = UINT64_MAX;
+    for (const Chunk &c : d.log) {
+        if (c.ticket == 2) last2 = std::max<uint64_t>(last2, c.seq);
+        if (c.ticket == 1) first1 = std::min<uint64_t>(first1, c.seq);
+    }
+    CHECK(first1 > last2);
+    // a small shot admitted now overtakes the large one at the next publication
+    s.submit(shot(3, 4096, 16, 1000));
+    s.admit([](Work &) { return 0; });
+    const size_t mark = d.log.size();
+    d.run(1, false);
+    d.collect();
+    d.publish();
+    CHECK(d.log.size() > mark && d.log[mark].ticket == 3);
+    // work left reaches zero exactly when the last chunk of every phase is out
+    for (int it = 0; it < 100000 && (s.find(1)->state != DONE || s.find(3)->state != DONE ||
+                                     s.find(2)->state != DONE); ++it) {
+        d.publish();
+        d.run(5, true);
+        d.collect();
+    }
+    for (uint64_t t = 1; t <= 3; ++t) CHECK(s.find(t)->state == DONE && std::abs(s.find(t)->work_left) < 1.0);
+    // split shots and backgrounds count their reduce and background phases
+    Scheduler u(1 << 30, 1 << 22, 8, n_wg, 1 << 16, POLICY_SHORTEST_REMAINING);
+    Device e(u);
+    u.submit(shot(4, 4096, 40, 50000, 8, 4096, 500));
+    u.admit([](Work &) { return 0; });
+    CHECK(u.find(4)->work_left == 40.0 * 256 * (50000 + 8 + 500));
+    for (int it = 0; it < 100000 && u.find(4)->state != DONE; ++it) {
+        e.publish();
+        e.run(3, true);
+        e.collect();
+    }
+    CHECK(u.find(4)->state == DONE && std::abs(u.find(4)->work_left) < 1.0);
+}
+
 static void check_cancel()
 {
     printf("cancel: queued shots only; the ones behind move up; space untouched\n");
@@ -370,6 +463,8 @@ int main()
     check_fifo_admission();
     check_units_and_depth();
     check_fair_share();
+    check_waiting_bound();
+    check_shortest_remaining();
     check_cancel();
     check_ring_sequence();
     check_ring_slot_reuse();

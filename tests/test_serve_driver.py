@@ -119,6 +119,7 @@ def test_poisson_arrivals_rate():
     ("precision", 5, xrt.XRT_EINVAL),
     ("shape", 3, xrt.XRT_EINVAL),
     ("idle_exit_us", 0.0, xrt.XRT_ERANGE),
+    ("policy", 2, xrt.XRT_EINVAL),
 ])
 def test_server_desc_validation(field, value, code):
     d = xrt.ServerDesc(C.sizeof(xrt.ServerDesc), 1 << 30, 16, xrt.XRT_MIXED, 0, xrt.XRT_F32, 0, 1000.0)
