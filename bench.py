@@ -351,13 +351,15 @@ def ensemble_bench(shot, steps, n_images=16):
                         "achieved_GBs": gbsb, "frac": gbsb / 8000.0}}
 
 
-def mixed_error(shot, img32):
+def image_error(shot, img):
+    """Max and RMS relative error of an image of the full shot against the
+    oracle on 256 seeded pixels (the same pixels for every image)."""
     import numpy as np
     import synth
     from oracle import oracle as o
     pix = synth.pixel_sample(shot, 256, 2024)
     ref = o.simulate(shot, pix, nthreads=host_threads())
-    x = img32[pix[:, 1], pix[:, 0]].astype(np.float64)
+    x = img[pix[:, 1], pix[:, 0]].astype(np.float64)
     r = np.abs(x - ref) / ref
     return float(r.max()), float(np.sqrt(np.mean(r * r)))
 
@@ -709,15 +711,18 @@ def main():
                      "issue_efficiency": ISSUE_SLOTS["fp64"] * terms / (kern_ms * 1e-3) / ISSUE_PEAK,
                      "sclk_during_timed_region": sclk.summary()},
     }
+    e64, r64 = image_error(shot, img64.cpu().numpy())
+    res["max_rel_err"], res["rms_rel_err"] = e64, r64
+    res["err_sample"] = "256 seeded pixels of the timed image against the oracle"
     log(f"fp64: {ms:.1f} ms/step (events {kern_ms:.1f} ms), {value:.1f} Gterm/s, "
-        f"{rf['achieved']:.1f} algorithmic TFLOP/s, roofline frac {rf['frac']:.3f}")
+        f"{rf['achieved']:.1f} algorithmic TFLOP/s, roofline frac {rf['frac']:.3f}, max rel err {e64:.2e}")
 
     if "mixed" in sections:
         img32, wall32, ev32 = time_form(shot, fh, "mixed", args.steps, args.warmup)
         k32 = sum(ev32) / len(ev32)
         v32 = terms / (wall32 / args.steps) / 1e9
         rf32 = roofline_of(FLOPS["spots"]["mixed"], terms / (k32 * 1e-3))
-        emax, erms = mixed_error(shot, img32.cpu().numpy())
+        emax, erms = image_error(shot, img32.cpu().numpy())
         res["mixed"] = {"value": v32, "unit": "Gterm/s", "ms_per_step": 1e3 * wall32 / args.steps,
                         "kernel_ms": k32, "roofline": rf32,
                         "counters": ctr["mixed"] if ctr else None,
