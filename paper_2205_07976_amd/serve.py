@@ -57,12 +57,12 @@ def run_stream(server, shots, arrivals, keep=None, on_done=None, timeout=600.0, 
             tickets[nxt] = server.submit(shots[nxt])
             pending[tickets[nxt]] = nxt
             nxt += 1
-        server.progress()
         finished = []
-        for t, i in pending.items():
-            info = server.info(t)
-            if info.state == 2:
-                finished.append((t, i, info))
+        if server.progress() > 0:  # shots seen finishing in this call: find them
+            for t, i in pending.items():
+                info = server.info(t)
+                if info.state == 2:
+                    finished.append((t, i, info))
         for t, i, info in finished:
             latency[i] = info.t_done - info.t_submit
             wait[i] = info.t_admit - info.t_submit

@@ -39,17 +39,21 @@ class FakeServer:
         return t
 
     def progress(self):
+        """As xrt_server_progress: returns the number of shots seen finishing
+        in this call."""
         now = self.now()
+        n_done = 0
         for t, s in self.shots.items():
             if s["admit"] >= 0 and s["done"] < 0 and now - s["admit"] >= self.service:
                 s["done"] = now
+                n_done += 1
         running = sum(1 for s in self.shots.values() if s["admit"] >= 0 and s["done"] < 0)
         while self.queue and running < self.slots:
             t = self.queue.pop(0)
             self.shots[t]["admit"] = now
             self.admit_order.append(t)
             running += 1
-        return 0
+        return n_done
 
     def info(self, t):
         s = self.shots[t]
