@@ -54,12 +54,16 @@ def drain(server, tickets, timeout=60.0):
             raise TimeoutError(f"states {states}")
 
 
-@pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_served_equal_standalone_in_mix_and_alone(precision):
+@pytest.mark.parametrize("precision,policy", [("mixed", "shortest_remaining"), ("fp64", "shortest_remaining"),
+                                              ("mixed", "fair_share"), ("fp64", "fair_share")])
+def test_served_equal_standalone_in_mix_and_alone(precision, policy):
+    """Ten shots at once (they share the persistent kernel, in the order of
+    either publication policy), then four alone: every image equals the
+    standalone call's bit for bit."""
     base, shots = small_served_shots(10)
     fh = xrt.Fhkl.from_shot(base)
     ref = [xrt.simulate(s, fh, precision=precision).cpu().numpy() for s in shots]
-    srv = xrt.Server(fh, hbm_budget=256 << 20, precision=precision)
+    srv = xrt.Server(fh, hbm_budget=256 << 20, precision=precision, policy=policy)
     tickets = [srv.submit(s) for s in shots]  # all at once: they share the kernel
     drain(srv, tickets)
     for i, t in enumerate(tickets):
@@ -76,10 +80,11 @@ def test_served_equal_standalone_in_mix_and_alone(precision):
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_served_short_rotation_lists(precision):
-    """The served kernel reads the spindle x domain matrices two at a time
-    (the loop unrolled by two, the next matrix read during the current
-    term): lists of 1, 2, 3 and 4 matrices, from domains alone and from
-    spindle steps x domains, give the standalone images bit for bit."""
+    """The served kernel reads the next spindle x domain matrix into the
+    registers of the current one as soon as the current term's h is formed
+    (the last term rereads its own): lists of 1 to 6 matrices, from domains
+    alone and from spindle steps x domains, give the standalone images bit
+    for bit."""
     base, shots = small_served_shots(8, seed=45, max_side=40)
     cases = [(1, 1), (2, 1), (3, 1), (4, 1), (1, 2), (3, 2), (2, 2), (1, 3)]  # (domains, spindle steps)
     shots = [s.replace(umats=s.umats[:1].repeat(m, axis=0) if len(s.umats) < m else s.umats[:m].copy(),
