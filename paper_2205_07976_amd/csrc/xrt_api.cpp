@@ -507,11 +507,17 @@ xrt_status make_plan(const xrt_detector *det, const xrt_beam *beam, const xrt_cr
     pl.o_src = 9 * pl.n_rot;
     pl.o_orig = pl.o_src + xrt::SRC_STRIDE * (size_t)beam->n_src;
     pl.o_q = pl.o_orig + (size_t)n_roi;  // one double slot holds one int32 pair
-    pl.host.assign(pl.o_q + (with_q ? 9 * pl.n_rot : 0), 0.0);
+    // adjoint: Q in binary64, then in binary32 (10 floats, 5 double slots, per rotation)
+    pl.host.assign(pl.o_q + (with_q ? 14 * pl.n_rot : 0), 0.0);
     build_cell_mats(xtal, pl.host.data());
     build_sources(beam, pl.host.data() + pl.o_src);
     std::memcpy(pl.host.data() + pl.o_orig, origins, sizeof(int32_t) * 2 * (size_t)n_roi);
-    if (with_q) build_rotations(xtal, pl.host.data() + pl.o_q);
+    if (with_q) {
+        build_rotations(xtal, pl.host.data() + pl.o_q);
+        float *q32 = reinterpret_cast<float *>(pl.host.data() + pl.o_q + 9 * pl.n_rot);
+        for (size_t r = 0; r < pl.n_rot; ++r)
+            for (int i = 0; i < 9; ++i) q32[10 * r + i] = (float)pl.host[pl.o_q + 9 * r + i];
+    }
 
     xrt::Params &p = pl.p;
     fill_params(det, beam, xtal, p);
@@ -547,6 +553,7 @@ void bind_tables(Plan &pl, double *dev)
     pl.p.src = dev + pl.o_src;
     pl.p.origins = reinterpret_cast<const int32_t *>(dev + pl.o_orig);
     pl.p.qmats = pl.host.size() > pl.o_q ? dev + pl.o_q : nullptr;
+    pl.p.qmats32 = pl.host.size() > pl.o_q ? reinterpret_cast<const float *>(dev + pl.o_q + 9 * pl.n_rot) : nullptr;
 }
 
 xrt_status check_call(int32_t precision, int32_t dtype, const void *ptr, const char *what)

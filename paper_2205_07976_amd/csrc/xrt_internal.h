@@ -64,6 +64,7 @@ struct Params {
     const double *src;     // [n_src][SRC_STRIDE]
     const int32_t *origins;  // [n_roi][2]
     const double *qmats;   // [n_rot][9] rotations umat_m R_k (adjoint only)
+    const float *qmats32;  // [n_rot][10] the same in binary32, 9 used (adjoint only)
     double m0[9];          // rows U a_i (adjoint only)
     double m2gk[3];        // -2 gk_i (adjoint only)
     double inv2N[3];       // 2 / N_i (adjoint only)

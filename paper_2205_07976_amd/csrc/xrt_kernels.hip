@@ -1156,7 +1156,11 @@ __device__ __forceinline__ void grad_term_f64(const Params &p, __amdgpu_buffer_r
 // binary32 sums of one (sample point, source) are rescaled with m and added
 // into binary64 as exp(m) times their value).  grad_prep_mixed forms what a
 // term needs up to its exponent and F^2, grad_add_mixed adds it; the term loop
-// raises the reference between the two, as the forward's does.
+// raises the reference between the two, as the forward's does.  h is formed
+// in binary64 from the forward's lab-frame matrix, h = M S (rows of M are
+// Q m0_i, so h_i = m0_i . Q^T S), and the S' = Q^T S that the dL/dM0 sums
+// multiply, in binary32 from binary32 copies of Q and S: it enters only the
+// binary32 derivative products.
 struct GradTerm {
     float f[3], Sf[3];
     double e;
@@ -1164,19 +1168,14 @@ struct GradTerm {
 };
 
 template <bool CLAMP>
-__device__ __forceinline__ void grad_prep_mixed(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *Q,
-                                                const double S[3], GradTerm &g)
+__device__ __forceinline__ void grad_prep_mixed(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *M,
+                                                const float *Q32, const double S[3], const float S32[3], GradTerm &g)
 {
-    double Sp[3], hr[3], fd[3];
+    double hr[3], fd[3], h[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        Sp[c] = __builtin_fma(Q[6 + c], S[2], __builtin_fma(Q[3 + c], S[1], Q[c] * S[0]));
-        g.Sf[c] = (float)Sp[c];
-    }
-    double h[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        h[i] = __builtin_fma(p.m0[3 * i + 2], Sp[2], __builtin_fma(p.m0[3 * i + 1], Sp[1], p.m0[3 * i] * Sp[0]));
+    for (int c = 0; c < 3; ++c)
+        g.Sf[c] = __builtin_fmaf(Q32[6 + c], S32[2], __builtin_fmaf(Q32[3 + c], S32[1], Q32[c] * S32[0]));
+    miller_fused(M, S, h);
     g.e = gauss_exponent(p, h, hr, fd);
 #pragma unroll
     for (int i = 0; i < 3; ++i) g.f[i] = (float)fd[i];
@@ -1206,12 +1205,13 @@ __device__ __forceinline__ void grad_rot_mixed(const Params &p, __amdgpu_buffer_
                                                float acc[13], GaussRef &ref)
 {
     const int n = p.n_rot;
+    const float S32[3] = {(float)S[0], (float)S[1], (float)S[2]};
     int r = 0;
     while (r < n) {
         GradTerm g;
         bool need = false;
         for (; r < n; ++r) {
-            grad_prep_mixed<CLAMP>(p, tab, p.qmats + 9 * r, S, g);
+            grad_prep_mixed<CLAMP>(p, tab, p.mats + 9 * r, p.qmats32 + 10 * r, S, S32, g);
             need = ref.needs_raise(g.e, g.F2);
             if (__builtin_amdgcn_ballot_w64(need)) break;
             grad_add_mixed(p, g, w, acc, ref);
