@@ -750,6 +750,7 @@ def main():
         res["background"]["counters"] = bgc
     if "ensemble" in sections:
         res["ensemble"] = ensemble_bench(shot, args.steps)
+        res["ensemble"]["counters"] = profile_keys("ensemble_full_detector_counters.txt")
     if "adjoint" in sections:
         res["adjoint"] = adjoint_bench(args.steps)
         res["adjoint"]["counters"] = profile_keys("grad_rois_counters.txt")
