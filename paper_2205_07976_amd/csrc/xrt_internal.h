@@ -16,11 +16,11 @@ namespace xrt {
 constexpr int SRC_STRIDE = 12;
 enum { SRC_DIR = 0, SRC_LAMBDA = 3, SRC_WEIGHT = 4, SRC_E = 5, SRC_B = 8, SRC_HIL = 11 };
 
-// Lower bound of |f| = |h - rint(h)| inside the binary64/32 lattice factor.
-// sin^2(pi N f)/sin^2(pi f) = N^2 (1 - (N^2-1) pi^2 f^2 / 3 + ...), so for
-// |f| <= 2^-32 it equals N^2 to a relative 3.3 N^2 2^-64 (<= 1.8e-13 at the
-// largest accepted N = 1000, <= 3e-16 at N = 40); replacing such f by 2^-32
-// removes the 0/0 at f = 0 without a branch or select.
+// Lower bound of |f| = |h - rint(h)| in the floored form of the sincg lattice
+// factor, the form a rotation sum falls back to when one of its terms met
+// f = 0 exactly (0/0).  sin^2(pi N f)/sin^2(pi f) = N^2 (1 - (N^2-1) pi^2 f^2
+// / 3 + ...), so for |f| <= 2^-32 it equals N^2 to a relative 3.3 N^2 2^-64
+// (<= 1.8e-13 at the largest accepted N = 1000, <= 3e-16 at N = 40).
 constexpr double F_FLOOR = 2.3283064365386963e-10;  // 2^-32
 
 // Layers of F_default around a structure-factor table.  When the host can

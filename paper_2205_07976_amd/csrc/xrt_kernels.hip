@@ -150,24 +150,35 @@ __device__ __forceinline__ float load_f32(__amdgpu_buffer_rsrc_t r, uint32_t off
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
 }
 
-// n / d for the lattice ratio: the hardware reciprocal (relative error below
-// 2^-24 on gfx950), one Newton step (error squared, ~2^-48) and a residual
-// correction of the quotient, which lands within an ulp or two for the normal
-// operands met here.  The lattice factor is not part of the bit-exact S/h
-// sequence.
-__device__ __forceinline__ double div_newton(double n, double d)
+// 1 / d for the lattice ratio: the hardware reciprocal (relative error below
+// 2^-24 on gfx950, measured 2^-24.4) and one Newton step, which squares that
+// error: below 2^-48, plus a rounding.  The ratio q = n (1/d) then carries a
+// relative error under 6e-15, and the term q^2 under 1.2e-14, far inside the
+// 1e-12 pixel tolerance.  The lattice factor is not part of the bit-exact
+// S/h sequence.
+__device__ __forceinline__ double recip_newton(double d)
 {
-    double r = __builtin_amdgcn_rcp(d);
-    r = __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
-    const double q = n * r;
-    return __builtin_fma(r, __builtin_fma(-d, q, n), q);
+    const double r = __builtin_amdgcn_rcp(d);
+    return __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
 }
 
 // ---------------------------------------------------------------------------
 // One term F^2 L^2, binary64, added into s: s + (F^2 q) q for the sincg
 // ratio q, s + F^2 L^2 for the Gaussian factor L^2 (one FMA each).
+//
+// The sincg ratio prod_i sin(pi g_i) / prod_i sin(pi f_i), with f = h - rint(h)
+// and g = N f - rint(N f), is even in each f_i, so the signed f serves.  It is
+// 0/0 when some f_i is exactly 0 (h_i an integer, e.g. S = 0 on the direct
+// beam), where the lattice factor takes its limit N_i^2.  FLOORED = false
+// evaluates the ratio as it stands: an exact zero gives NaN (0 times the
+// infinite reciprocal), which the caller detects on the finished sum and
+// answers by summing again with FLOORED = true, where |f| is replaced by
+// max(|f|, 2^-32) and the ratio is within 3.3 N^2 2^-64 of its limit.  Any
+// other f is at least ulp(h) (|h| >= 1/2) or, for |h| < 1/2, a product of
+// matrix entries and a nonzero S component, so the denominator stays far
+// above the binary64 underflow and the unfloored value is the better one.
 // ---------------------------------------------------------------------------
-template <int SHAPE, bool CLAMP>
+template <int SHAPE, bool CLAMP, bool FLOORED>
 __device__ __forceinline__ double term_f64_add(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3],
                                                double s)
 {
@@ -177,13 +188,13 @@ __device__ __forceinline__ double term_f64_add(const Params &p, __amdgpu_buffer_
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             hr[i] = __builtin_rint(h[i]);
-            const double fa = __builtin_fmax(__builtin_fabs(h[i] - hr[i]), F_FLOOR);
-            const double t = p.N[i] * fa;
+            const double f = FLOORED ? __builtin_fmax(__builtin_fabs(h[i] - hr[i]), F_FLOOR) : h[i] - hr[i];
+            const double t = p.N[i] * f;
             const double g = t - __builtin_rint(t);
             num *= sinpi_reduced(g);
-            den *= sinpi_reduced(fa);
+            den *= sinpi_reduced(f);
         }
-        const double q = div_newton(num, den);
+        const double q = num * recip_newton(den);
         const double F2 = load_f64(tab, table_offset<CLAMP>(p, hr, p.off64));
         return __builtin_fma(F2 * q, q, s);
     } else {
@@ -200,22 +211,28 @@ __device__ __forceinline__ double term_f64_add(const Params &p, __amdgpu_buffer_
 }
 
 // One sincg term, mixed: h, f and g in binary64 (they decide the
-// conditioning), everything after the reduced arguments in binary32.
-template <bool CLAMP>
-__device__ __forceinline__ float term_mixed_sincg(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3])
+// conditioning), everything after the reduced arguments in binary32.  As in
+// term_f64_add, FLOORED = false takes the signed f as it stands; ok is false
+// when the binary32 denominator is below 2^-100 (an exact integer index gives
+// 0, and denominators in the binary32 denormal range have lost precision),
+// and the caller then sums again with FLOORED = true.
+template <bool CLAMP, bool FLOORED>
+__device__ __forceinline__ float term_mixed_sincg(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3],
+                                                  bool &ok)
 {
     double hr[3];
     float num = 1.0f, den = 1.0f;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         hr[i] = __builtin_rint(h[i]);
-        const double fa = __builtin_fmax(__builtin_fabs(h[i] - hr[i]), F_FLOOR);
+        const double fa = FLOORED ? __builtin_fmax(__builtin_fabs(h[i] - hr[i]), F_FLOOR) : h[i] - hr[i];
         const double t = p.N[i] * fa;
         const float g = (float)(t - __builtin_rint(t));
         const float f = (float)fa;
         num *= sinpi_reduced(g);
         den *= sinpi_reduced(f);
     }
+    ok = __builtin_fabsf(den) >= 0x1p-100f;
     const float q = num * __builtin_amdgcn_rcpf(den);
     return load_f32(tab, table_offset<CLAMP>(p, hr, p.off32)) * (q * q);
 }
@@ -321,6 +338,7 @@ template <int PREC, int SHAPE, bool CLAMP>
 struct RotSum {
     double s64 = 0.0;
     float s = 0.0f, c = 0.0f;
+    bool redo = false;  // mixed sincg: some term needs the floored ratio
     GaussRef ref;  // mixed Gaussian: reference exponent
     // h = M S by the sequence of this precision
     static __device__ __forceinline__ void hkl(const double M[9], const double S[3], double h[3])
@@ -330,19 +348,23 @@ struct RotSum {
         else
             miller_fused(M, S, h);
     }
+    template <bool FLOORED = false>
     __device__ __forceinline__ void add(const Params &p, __amdgpu_buffer_rsrc_t tab, const double M[9],
                                         const double S[3])
     {
         double h[3];
         hkl(M, S, h);
-        add_h(p, tab, h);
+        add_h<FLOORED>(p, tab, h);
     }
+    template <bool FLOORED = false>
     __device__ __forceinline__ void add_h(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3])
     {
         if constexpr (PREC == XRT_FP64) {
-            s64 = term_f64_add<SHAPE, CLAMP>(p, tab, h, s64);
+            s64 = term_f64_add<SHAPE, CLAMP, FLOORED>(p, tab, h, s64);
         } else if constexpr (SHAPE == XRT_SHAPE_SINCG) {
-            kahan_add(s, c, term_mixed_sincg<CLAMP>(p, tab, h));
+            bool ok;
+            kahan_add(s, c, term_mixed_sincg<CLAMP, FLOORED>(p, tab, h, ok));
+            if (!FLOORED) redo |= !ok;
         } else {
             double e;
             float F2;
@@ -387,6 +409,26 @@ __device__ __forceinline__ void load9(double m[9], const double *src)
     for (int q = 0; q < 9; ++q) m[q] = src[q];
 }
 
+// The plain sum over r of the terms at h = M_r S.
+template <bool FLOORED, bool PF, class Acc>
+__device__ __forceinline__ void rot_loop(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *mats,
+                                         const double S[3], Acc &acc)
+{
+    const int n = p.n_rot;
+    if (PF) {
+        double m[9];
+        load9(m, mats);
+        for (int r = 0; r < n; ++r) {
+            double h[3];
+            acc.hkl(m, S, h);
+            load9(m, mats + 9 * (r + 1 < n ? r + 1 : r));
+            acc.template add_h<FLOORED>(p, tab, h);
+        }
+    } else {
+        for (int r = 0; r < n; ++r) acc.template add<FLOORED>(p, tab, mats + 9 * r, S);
+    }
+}
+
 // Without PF the matrix of term r is read where it is used (scalar loads in
 // the standalone kernel).  With PF (tables in LDS) the matrix of term r is
 // dead once h = M S is formed, so the reads of matrix r + 1 are issued into
@@ -428,17 +470,20 @@ __device__ __forceinline__ void rot_sum(const Params &p, __amdgpu_buffer_rsrc_t 
         }
         return;
     }
-    if (PF) {
-        double m[9];
-        load9(m, mats);
-        for (int r = 0; r < n; ++r) {
-            double h[3];
-            acc.hkl(m, S, h);
-            load9(m, mats + 9 * (r + 1 < n ? r + 1 : r));
-            acc.add_h(p, tab, h);
+    rot_loop<false, PF>(p, tab, mats, S, acc);
+    // a term with an exact integer index on this lane (0/0), or a binary32
+    // denominator below 2^-100: the sum again with the floored ratio
+    // (term_f64_add, term_mixed_sincg)
+    if constexpr (PREC == XRT_FP64 && SHAPE == XRT_SHAPE_SINCG) {
+        if (!__builtin_isfinite(acc.s64)) {
+            acc.s64 = 0.0;
+            rot_loop<true, PF>(p, tab, mats, S, acc);
         }
-    } else {
-        for (int r = 0; r < n; ++r) acc.add(p, tab, mats + 9 * r, S);
+    } else if constexpr (SHAPE == XRT_SHAPE_SINCG) {
+        if (acc.redo) {
+            acc.s = acc.c = 0.0f;
+            rot_loop<true, PF>(p, tab, mats, S, acc);
+        }
     }
 }
 

@@ -326,6 +326,32 @@ def micro_shot(seed: int = 10, shape: int = SHAPE_SINCG) -> Shot:
     )
 
 
+def direct_beam_shot(seed: int = 12) -> Shot:
+    """32 x 32 detector of 2^-13 m pixels at 2^-3 m, the beam through the
+    centre of pixel (16, 16), oversample 3: the middle sub-pixel of that pixel
+    lies exactly on the beam, so for the on-axis source its scattering vector
+    is exactly 0 and so is every fractional index (h = 0: the lattice factor
+    at its f = 0 limit); a second source off axis, 3 mosaic domains, 2 phi
+    steps, N = (5, 6, 7)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = 2.0 ** -13
+    dirs = np.array([[0.0, 0.0, 1.0], [1e-3, 0.0, 1.0]])
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    F = friedel_table(rng.uniform(10.0, 1000.0, (9, 9, 9)))
+    return Shot(
+        n_fast=32, n_slow=32, pixel=p, distance=0.125,
+        beam_f=16.5 * p, beam_s=16.5 * p,
+        oversample=3, n_layers=1, layer_dt=0.0,
+        src_dir=dirs, src_lambda=np.array([1.30, 1.31]), src_weight=np.array([0.6, 0.4]),
+        kahn=0.0,
+        cell=orthorhombic_cell(50.0, 60.0, 70.0), U=random_rotation(rng),
+        umats=mosaic_umats(rng, 3, 0.5), n_phi=2, phi0=0.01, dphi=0.02,
+        spindle=np.array([0.0, 1.0, 0.0]),
+        N=np.array([5.0, 6.0, 7.0]), shape=SHAPE_SINCG,
+        hkl_min=np.array([-4, -4, -4]), F=F, F_default=0.0,
+    )
+
+
 def roi_shot(seed: int = 5, n_roi: int = 512, size: int = 32, lam0: float = 1.30):
     """The full-size crystal with the Gaussian shape (N = 20) and n_roi
     non-overlapping size x size regions of interest around its predicted

@@ -6,6 +6,7 @@ must agree bit for bit, which is what keeps ill-conditioned single-term
 pixels inside 1e-12.
 """
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -268,6 +269,40 @@ def test_exact_bragg_on_gpu():
     assert abs(g - expect) / expect <= FP64_TOL
     m = gpu_image(shot, "mixed", roi=(90, 91, 40, 41))[0, 0]
     assert abs(m - expect) / expect <= MIXED_TOL
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_direct_beam_zero_index(precision, tol):
+    """Terms whose fractional indices are exactly 0 (S = 0 on the direct
+    beam): the ratio of sines is 0/0 there, and the kernels sum such a
+    rotation loop again with the floored ratio.  The whole image (the beam
+    pixel's on-axis sub-pixel takes that path, the rest do not) against the
+    oracle, standalone and served; and with a single on-axis sample point the
+    beam pixel against its closed form r_e^2 Phi F(000)^2 (Na Nb Nc)^2 dOmega."""
+    shot = synth.direct_beam_shot()
+    img = gpu_image(shot, precision)
+    r = compare(img, o.simulate(shot))
+    say("direct beam", precision, r)
+    assert r["zeros_ok"] and r["max_rel"] <= tol
+    srv = xrt.Server(xrt.Fhkl.from_shot(shot), hbm_budget=64 << 20, precision=precision)
+    try:
+        t = srv.submit(shot)
+        deadline = time.monotonic() + 60.0
+        while srv.progress() == 0:
+            assert time.monotonic() < deadline, "served shot did not finish"
+        served = srv.image(t).cpu().numpy().astype(np.float64)
+        srv.release(t)
+    finally:
+        srv.close()
+    assert np.array_equal(served, img)
+    from tests import geometry as geo
+    one = shot.replace(oversample=1, src_dir=shot.src_dir[:1], src_lambda=shot.src_lambda[:1],
+                       src_weight=np.array([1.0]))
+    g = gpu_image(one, precision, roi=(16, 17, 16, 17))[0, 0]
+    F = one.F[4, 4, 4]
+    expect = (geo.R_E ** 2 * one.fluence * F * F * (5 * 6 * 7) ** 2
+              * geo.flat_solid_angle(one.pixel, 0.0, 0.0, one.distance))
+    assert abs(g - expect) / expect <= tol
 
 
 def test_clamped_index_path():

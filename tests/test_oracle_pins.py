@@ -34,6 +34,25 @@ def test_exact_bragg_peak(pix, hkl, kahn):
     assert rel(val, expect) <= 1e-12
 
 
+def test_direct_beam_zero_index():
+    """On the direct beam S = 0 exactly, so every fractional index is 0 and
+    each sincg factor takes its f = 0 limit N: with one on-axis source and one
+    sample point per pixel the beam pixel is r_e^2 Phi s F(000)^2 (Na Nb Nc)^2
+    dOmega (P = 1 at zero scattering angle).  The input generator's shot
+    really puts S = 0 on the middle sub-pixel of pixel (16, 16)."""
+    shot = synth.direct_beam_shot()
+    idx = np.array([[16, 16, 4, 0, 0, r] for r in range(shot.n_phi * shot.n_mos)], np.int32)
+    S, h = o.trace(shot, idx)
+    assert np.all(S == 0.0) and np.all(h == 0.0)
+    one = shot.replace(oversample=1, src_dir=shot.src_dir[:1], src_lambda=shot.src_lambda[:1],
+                       src_weight=np.array([1.0]))
+    val = o.simulate(one, np.array([[16, 16]], np.int32))[0]
+    F = one.F[4, 4, 4]
+    expect = (geo.R_E ** 2 * one.fluence * one.scale * F * F * (5 * 6 * 7) ** 2
+              * geo.flat_solid_angle(one.pixel, 0.0, 0.0, one.distance))
+    assert rel(val, expect) <= 1e-12
+
+
 # ---------------------------------------------------------------- pin 2 ----
 def test_unit_crystal_closed_form():
     """Na = Nb = Nc = 1 makes the lattice factor 1; with a constant structure
