@@ -180,7 +180,7 @@ __device__ __forceinline__ double recip_newton(double d)
 // ---------------------------------------------------------------------------
 template <int SHAPE, bool CLAMP, bool FLOORED>
 __device__ __forceinline__ double term_f64_add(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3],
-                                               double s)
+                                               double s, double c6 = SINPI_C6)
 {
     double hr[3];
     if (SHAPE == XRT_SHAPE_SINCG) {
@@ -191,8 +191,8 @@ __device__ __forceinline__ double term_f64_add(const Params &p, __amdgpu_buffer_
             const double f = FLOORED ? __builtin_fmax(__builtin_fabs(h[i] - hr[i]), F_FLOOR) : h[i] - hr[i];
             const double t = p.N[i] * f;
             const double g = t - __builtin_rint(t);
-            num *= sinpi_reduced(g);
-            den *= sinpi_reduced(f);
+            num *= sinpi_reduced(g, c6);
+            den *= sinpi_reduced(f, c6);
         }
         const double q = num * recip_newton(den);
         const double F2 = load_f64(tab, table_offset<CLAMP>(p, hr, p.off64));
@@ -339,6 +339,7 @@ struct RotSum {
     double s64 = 0.0;
     float s = 0.0f, c = 0.0f;
     bool redo = false;  // mixed sincg: some term needs the floored ratio
+    double c6 = SINPI_C6;  // binary64 sincg: sinpi_over_x's c6, set by rot_loop
     GaussRef ref;  // mixed Gaussian: reference exponent
     // h = M S by the sequence of this precision
     static __device__ __forceinline__ void hkl(const double M[9], const double S[3], double h[3])
@@ -360,7 +361,7 @@ struct RotSum {
     __device__ __forceinline__ void add_h(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3])
     {
         if constexpr (PREC == XRT_FP64) {
-            s64 = term_f64_add<SHAPE, CLAMP, FLOORED>(p, tab, h, s64);
+            s64 = term_f64_add<SHAPE, CLAMP, FLOORED>(p, tab, h, s64, c6);
         } else if constexpr (SHAPE == XRT_SHAPE_SINCG) {
             bool ok;
             kahan_add(s, c, term_mixed_sincg<CLAMP, FLOORED>(p, tab, h, ok));
@@ -415,6 +416,7 @@ __device__ __forceinline__ void rot_loop(const Params &p, __amdgpu_buffer_rsrc_t
                                          const double S[3], Acc &acc)
 {
     const int n = p.n_rot;
+    acc.c6 = sinpi_c6_reg();
     if (PF) {
         double m[9];
         load9(m, mats);

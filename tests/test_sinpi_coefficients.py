@@ -18,10 +18,13 @@ def coefficients(kind):
     """Horner coefficients, highest degree first, of the double or float
     sinpi_over_x in the header."""
     src = open(HEADER).read()
-    sig = "double sinpi_over_x(double y)" if kind == "f64" else "float sinpi_over_x(float y)"
+    sig = "double sinpi_over_x(double y, double c6" if kind == "f64" else "float sinpi_over_x(float y)"
     body = src[src.index(sig):]
     body = body[:body.index("return p;")]
     nums = re.findall(r"[-+]?\d+\.\d+(?:e[-+]?\d+)?", body)
+    if kind == "f64":  # the first step's constant term is the named SINPI_C6
+        c6 = re.search(r"constexpr double SINPI_C6 = ([-+]?\d+\.\d+(?:e[-+]?\d+)?);", src).group(1)
+        nums.insert(1, c6)
     return [mp.mpf(float(n.rstrip("f"))) if kind == "f64" else mp.mpf(float(n)) for n in nums]
 
 
