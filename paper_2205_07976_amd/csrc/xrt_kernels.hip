@@ -150,6 +150,18 @@ __device__ __forceinline__ float load_f32(__amdgpu_buffer_rsrc_t r, uint32_t off
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
 }
 
+// x in a vector register, opaque to the compiler.  A loop constant that an
+// instruction needs in a vector register (its other constant operand takes
+// the one scalar read an instruction has) is otherwise moved there again on
+// every pass; passed through this once before the loop, it stays in one
+// register.  Not volatile: a volatile asm statement counts as a memory side
+// effect, and the loops' matrix reads would then leave the scalar cache.
+__device__ __forceinline__ double vreg(double x)
+{
+    asm("" : "+v"(x));
+    return x;
+}
+
 // 1 / d for the lattice ratio: the hardware reciprocal (relative error below
 // 2^-24 on gfx950, measured 2^-24.4) and one Newton step, which squares that
 // error: below 2^-48, plus a rounding.  The ratio q = n (1/d) then carries a
@@ -180,7 +192,7 @@ __device__ __forceinline__ double recip_newton(double d)
 // ---------------------------------------------------------------------------
 template <int SHAPE, bool CLAMP, bool FLOORED>
 __device__ __forceinline__ double term_f64_add(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3],
-                                               double s, double c6 = SINPI_C6)
+                                               double s, double c6 = SINPI_C6, double e0 = 0.0)
 {
     double hr[3];
     if (SHAPE == XRT_SHAPE_SINCG) {
@@ -198,7 +210,7 @@ __device__ __forceinline__ double term_f64_add(const Params &p, __amdgpu_buffer_
         const double F2 = load_f64(tab, table_offset<CLAMP>(p, hr, p.off64));
         return __builtin_fma(F2 * q, q, s);
     } else {
-        double e = p.ln_n2;
+        double e = e0;  // ln(Na^2 Nb^2 Nc^2), held in a register by the caller's loop
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             hr[i] = __builtin_rint(h[i]);
@@ -239,10 +251,11 @@ __device__ __forceinline__ float term_mixed_sincg(const Params &p, __amdgpu_buff
 
 // The Gaussian lattice exponent e = ln(Na^2 Nb^2 Nc^2) - sum_i gk_i f_i^2 of
 // h, in binary64 (the same sequence as the binary64 term), with the rounded
-// indices hr and the reduced arguments f.
-__device__ __forceinline__ double gauss_exponent(const Params &p, const double h[3], double hr[3], double f[3])
+// indices hr and the reduced arguments f; e0 is ln(Na^2 Nb^2 Nc^2).
+__device__ __forceinline__ double gauss_exponent(const Params &p, const double h[3], double hr[3], double f[3],
+                                                 double e0)
 {
-    double e = p.ln_n2;
+    double e = e0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         hr[i] = __builtin_rint(h[i]);
@@ -340,6 +353,7 @@ struct RotSum {
     float s = 0.0f, c = 0.0f;
     bool redo = false;  // mixed sincg: some term needs the floored ratio
     double c6 = SINPI_C6;  // binary64 sincg: sinpi_over_x's c6, set by rot_loop
+    double e0 = 0.0;       // Gaussian: ln(Na^2 Nb^2 Nc^2), set by the term loops
     GaussRef ref;  // mixed Gaussian: reference exponent
     // h = M S by the sequence of this precision
     static __device__ __forceinline__ void hkl(const double M[9], const double S[3], double h[3])
@@ -361,7 +375,7 @@ struct RotSum {
     __device__ __forceinline__ void add_h(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3])
     {
         if constexpr (PREC == XRT_FP64) {
-            s64 = term_f64_add<SHAPE, CLAMP, FLOORED>(p, tab, h, s64, c6);
+            s64 = term_f64_add<SHAPE, CLAMP, FLOORED>(p, tab, h, s64, c6, e0);
         } else if constexpr (SHAPE == XRT_SHAPE_SINCG) {
             bool ok;
             kahan_add(s, c, term_mixed_sincg<CLAMP, FLOORED>(p, tab, h, ok));
@@ -369,7 +383,7 @@ struct RotSum {
         } else {
             double e;
             float F2;
-            gauss_term(p, tab, h, e, F2);
+            gauss_term(p, tab, h, e0, e, F2);
             if (ref.needs_raise(e, F2)) rescale(ref.raise(e));
             add_gauss(e, F2);
         }
@@ -377,10 +391,10 @@ struct RotSum {
     // Mixed Gaussian: the exponent and F^2 of the term at h; the sums scaled
     // by k; the term F^2 exp(e - m) added.
     static __device__ __forceinline__ void gauss_term(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3],
-                                                      double &e, float &F2)
+                                                      double e0, double &e, float &F2)
     {
         double hr[3], f[3];
-        e = gauss_exponent(p, h, hr, f);
+        e = gauss_exponent(p, h, hr, f, e0);
         F2 = load_f32(tab, table_offset<CLAMP>(p, hr, p.off32));
     }
     __device__ __forceinline__ void rescale(float k)
@@ -416,7 +430,8 @@ __device__ __forceinline__ void rot_loop(const Params &p, __amdgpu_buffer_rsrc_t
                                          const double S[3], Acc &acc)
 {
     const int n = p.n_rot;
-    acc.c6 = sinpi_c6_reg();
+    acc.c6 = vreg(SINPI_C6);
+    acc.e0 = vreg(p.ln_n2);
     if (PF) {
         double m[9];
         load9(m, mats);
@@ -447,6 +462,7 @@ __device__ __forceinline__ void rot_sum(const Params &p, __amdgpu_buffer_rsrc_t 
         // done outside it
         double m[9];
         if (PF) load9(m, mats);
+        acc.e0 = vreg(p.ln_n2);
         int r = 0;
         while (r < n) {
             double e = 0.0;
@@ -460,7 +476,7 @@ __device__ __forceinline__ void rot_sum(const Params &p, __amdgpu_buffer_rsrc_t 
                 } else {
                     acc.hkl(mats + 9 * r, S, h);
                 }
-                acc.gauss_term(p, tab, h, e, F2);
+                acc.gauss_term(p, tab, h, acc.e0, e, F2);
                 need = acc.ref.needs_raise(e, F2);
                 if (__builtin_amdgcn_ballot_w64(need)) break;
                 acc.add_gauss(e, F2);
@@ -1173,12 +1189,12 @@ hipError_t launch_serve(const ServeArgs &a, int precision, int shape, int n_wg, 
 // ---------------------------------------------------------------------------
 template <bool CLAMP>
 __device__ __forceinline__ void grad_term_f64(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *Q,
-                                              const double S[3], double w, double acc[13])
+                                              const double S[3], double w, double acc[13], double e0)
 {
     double Sp[3], hr[3], f[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) Sp[c] = __builtin_fma(Q[6 + c], S[2], __builtin_fma(Q[3 + c], S[1], Q[c] * S[0]));
-    double e = p.ln_n2;
+    double e = e0;  // ln(Na^2 Nb^2 Nc^2)
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const double h = __builtin_fma(p.m0[3 * i + 2], Sp[2], __builtin_fma(p.m0[3 * i + 1], Sp[1], p.m0[3 * i] * Sp[0]));
@@ -1216,14 +1232,15 @@ struct GradTerm {
 
 template <bool CLAMP>
 __device__ __forceinline__ void grad_prep_mixed(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *M,
-                                                const float *Q32, const double S[3], const float S32[3], GradTerm &g)
+                                                const float *Q32, const double S[3], const float S32[3], double e0,
+                                                GradTerm &g)
 {
     double hr[3], fd[3], h[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
         g.Sf[c] = __builtin_fmaf(Q32[6 + c], S32[2], __builtin_fmaf(Q32[3 + c], S32[1], Q32[c] * S32[0]));
     miller_fused(M, S, h);
-    g.e = gauss_exponent(p, h, hr, fd);
+    g.e = gauss_exponent(p, h, hr, fd, e0);
 #pragma unroll
     for (int i = 0; i < 3; ++i) g.f[i] = (float)fd[i];
     g.F2 = load_f32(tab, table_offset<CLAMP>(p, hr, p.off32));
@@ -1253,12 +1270,13 @@ __device__ __forceinline__ void grad_rot_mixed(const Params &p, __amdgpu_buffer_
 {
     const int n = p.n_rot;
     const float S32[3] = {(float)S[0], (float)S[1], (float)S[2]};
+    const double e0 = vreg(p.ln_n2);
     int r = 0;
     while (r < n) {
         GradTerm g;
         bool need = false;
         for (; r < n; ++r) {
-            grad_prep_mixed<CLAMP>(p, tab, p.mats + 9 * r, p.qmats32 + 10 * r, S, S32, g);
+            grad_prep_mixed<CLAMP>(p, tab, p.mats + 9 * r, p.qmats32 + 10 * r, S, S32, e0, g);
             need = ref.needs_raise(g.e, g.F2);
             if (__builtin_amdgcn_ballot_w64(need)) break;
             grad_add_mixed(p, g, w, acc, ref);
@@ -1312,7 +1330,9 @@ __global__ __launch_bounds__(BLOCK) void grad_kernel(const Params p, const void 
                     scatter(src, d, S);
                     const double w = src[SRC_WEIGHT] * polarization(src, d, p.kahn) * wgeo;
                     if (PREC == XRT_FP64) {
-                        for (int r = 0; r < p.n_rot; ++r) grad_term_f64<CLAMP>(p, tab, p.qmats + 9 * r, S, w, acc);
+                        const double e0 = vreg(p.ln_n2);
+                        for (int r = 0; r < p.n_rot; ++r)
+                            grad_term_f64<CLAMP>(p, tab, p.qmats + 9 * r, S, w, acc, e0);
                     } else {
                         float a32[13];
 #pragma unroll

@@ -42,9 +42,10 @@ __device__ __forceinline__ double fma_svv(double a, double b, double c)
 constexpr double SINPI_C6 = 0.00046597761697049093;
 
 // y = x^2, returns sin(pi x)/x.  c6 is SINPI_C6; a loop that evaluates many
-// sines passes a copy that the compiler cannot see through (sinpi_c6_reg),
-// which then stays in one vector register for the whole loop instead of
-// being moved into one again for every term.
+// sines passes a copy that the compiler cannot see through, which then stays
+// in one vector register for the whole loop instead of being moved into one
+// again for every term (the first step's other constant takes the one scalar
+// operand an instruction may read).
 __device__ __forceinline__ double sinpi_over_x(double y, double c6 = SINPI_C6)
 {
     double p = fma_svv(-2.1122952923797757e-05, y, c6);
@@ -118,16 +119,6 @@ __device__ __forceinline__ double expm1_f64(double x)
     const double r = exp_reduce(x, n);
     const double q = exp_q(r);
     return n == 0.0 ? r * q : __builtin_ldexp(__builtin_fma(q, r, 1.0), (int)n) - 1.0;
-}
-
-// SINPI_C6 in a vector register, opaque to the compiler (no rematerialization).
-// Not volatile: a volatile asm statement counts as a memory side effect, and
-// the loop's matrix reads would then leave the scalar cache.
-__device__ __forceinline__ double sinpi_c6_reg()
-{
-    double c = SINPI_C6;
-    asm("" : "+v"(c));
-    return c;
 }
 
 // sin(pi x) for |x| <= 1/2, composed as the lattice factor uses it.
