@@ -63,6 +63,8 @@ def err():
     ("n_layers", 3, xrt.XRT_EINVAL),        # layer_dt == 0 with 3 layers
     ("roi_f1", 129, xrt.XRT_EINVAL),
     ("roi_s0", 128, xrt.XRT_EINVAL),
+    ("roi_f1", 0, xrt.XRT_EINVAL),          # empty region: f0 == f1
+    ("roi_s1", 0, xrt.XRT_EINVAL),          # empty region: s0 == s1
 ])
 def test_detector_validation(field, value, code):
     st = xrt.ShotStructs(synth.tiny_shot())
@@ -101,6 +103,12 @@ def test_beam_validation():
     st = xrt.ShotStructs(shot.replace(evec=np.array([0.0, 0.0, 1.0])))  # along the beam
     assert _call_simulate(st) == xrt.XRT_EINVAL
     st = xrt.ShotStructs(shot.replace(src_dir=np.array([[0.0, 0.0, 2.0]])))
+    assert _call_simulate(st) == xrt.XRT_EINVAL
+    st = xrt.ShotStructs(shot)
+    st.beam.n_src = 0  # no sources: an empty sum is refused, not silently zero
+    assert _call_simulate(st) == xrt.XRT_ERANGE
+    st = xrt.ShotStructs(shot)
+    st.xtal.n_mos = 0
     assert _call_simulate(st) == xrt.XRT_EINVAL
 
 
