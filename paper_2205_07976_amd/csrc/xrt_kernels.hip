@@ -349,6 +349,7 @@ __device__ __forceinline__ Pixel tile_pixel(const Params &p, int tile)
 // binary32 one in the mixed form.
 template <int PREC, int SHAPE, bool CLAMP>
 struct RotSum {
+    static constexpr bool KAHAN_SINCG = PREC == XRT_MIXED && SHAPE == XRT_SHAPE_SINCG;
     double s64 = 0.0;
     float s = 0.0f, c = 0.0f;
     bool redo = false;  // mixed sincg: some term needs the floored ratio
@@ -441,6 +442,11 @@ __device__ __forceinline__ void rot_loop(const Params &p, __amdgpu_buffer_rsrc_t
             load9(m, mats + 9 * (r + 1 < n ? r + 1 : r));
             acc.template add_h<FLOORED>(p, tab, h);
         }
+    } else if constexpr (Acc::KAHAN_SINCG) {
+        // by two: the Kahan sum's registers then alternate instead of being
+        // copied back once per term
+#pragma unroll 2
+        for (int r = 0; r < n; ++r) acc.template add<FLOORED>(p, tab, mats + 9 * r, S);
     } else {
         for (int r = 0; r < n; ++r) acc.template add<FLOORED>(p, tab, mats + 9 * r, S);
     }
