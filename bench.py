@@ -77,8 +77,11 @@ def roofline_of(flops, terms_per_s):
 # the binary64 and mixed sincg loops weighted by their measured issue cost on
 # gfx950, in binary32-lane-op units (binary32 op 1, binary64 op or conversion
 # 2, binary32 transcendental 4, binary64 reciprocal 8); it follows the
-# kernel, so a loop issued without stalls sits near 1.
-ISSUE_SLOTS = {"fp64": 204, "mixed": 129}
+# kernel, so a loop issued without stalls sits near 1.  binary64 loop: 93
+# binary64 operations and one reciprocal per term (194); mixed: 33 binary64
+# operations and conversions, 48 binary32 operations and one binary32
+# reciprocal (118).
+ISSUE_SLOTS = {"fp64": 194, "mixed": 118}
 ISSUE_PEAK = 256 * 4 * 32 * 2.4e9
 
 HERE = os.path.dirname(os.path.abspath(__file__))
