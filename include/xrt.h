@@ -318,7 +318,8 @@ xrt_status xrt_add_images(double *dev_acc, int32_t acc_nf, int32_t acc_ns,
  * The paper runs many simulations per GPU and lets several producers share a
  * GPU to hide latency (section IV, ranks per GPU).  A server owns one arena of
  * device memory (its HBM budget, holding the images and, for shots whose
- * per-pixel sums are split, their part sums) and borrows the structure
+ * per-pixel sums are split or run in segments, their part sums and running
+ * sums) and borrows the structure
  * factors (shared by every shot); shot descriptors and tables sit in pinned
  * host memory that the kernel reads directly.  Submitted shots wait in
  * arrival order; a shot is admitted when its footprint fits in the arena and
@@ -369,6 +370,18 @@ typedef struct xrt_server_desc {
                                xrt_simulate_background with accumulate, bit
                                for bit); read during xrt_server_create only */
     int32_t policy;         /* XRT_SERVE_FAIR_SHARE or XRT_SERVE_SHORTEST_REMAINING */
+    int64_t segment_terms;  /* pixel-terms of a 16 x 16 tile's sums (or of one
+                               part of split sums) that one chunk carries at
+                               most: a heavier tile's sums run as consecutive
+                               segments of its outer iterations, each picking
+                               up the running sums the previous one left, so a
+                               chunk never holds a workgroup much longer than
+                               this and a shot that arrives meanwhile waits
+                               less for one; the images keep their bits.  0 =
+                               the default 2^22 (a few ms of one workgroup),
+                               else in [2^10, 2^40].  Segments need 8 bytes of
+                               the device arena per pixel (per part) of a
+                               segmented shot. */
 } xrt_server_desc;
 
 enum { XRT_SHOT_QUEUED = 0, XRT_SHOT_RUNNING = 1, XRT_SHOT_DONE = 2 };

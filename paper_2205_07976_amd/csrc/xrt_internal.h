@@ -104,8 +104,10 @@ struct ShotDesc {
     uint64_t partial_bytes; // (split > 1 only)
     int32_t roi_f0, roi_s0;
     int32_t clamp;          // 0: every rint(h) of the shot is proven inside the padded table
-    int32_t pad2;
+    int32_t n_seg;          // segments of each unit's outer iterations (>= 1)
     double bg_norm;         // r_e^2 fluence molecules / O^2 of the server's background
+    uint64_t state_off;     // byte offset of the running sums between segments
+    uint64_t state_bytes;   // (n_seg > 1 only): [unit][lane], 8 bytes each
 };
 
 struct ServeChunk {         // written by the host before the tail publishes it
@@ -117,7 +119,8 @@ struct ServeChunk {         // written by the host before the tail publishes it
     int32_t kind;           // CHUNK_COMPUTE: units tile * split + part;
                             // CHUNK_REDUCE: tiles whose parts are all done;
                             // CHUNK_BACKGROUND: tiles of a complete image
-    int32_t pad;
+    int32_t seg;            // CHUNK_COMPUTE: the segment of the units' outer
+                            // iterations (every earlier one is done)
 };
 
 struct ServeCtrl {          // pinned host memory, written by the host

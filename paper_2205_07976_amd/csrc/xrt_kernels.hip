@@ -511,21 +511,56 @@ __device__ __forceinline__ void rot_sum(const Params &p, __amdgpu_buffer_rsrc_t 
     }
 }
 
-// The per-pixel sum of pixel (i_f, i_s), not normalised, over the part
-// [q0, q1) of its outer iterations q = ((u O + v) T + t) n_src + j (sub-pixel
-// (u, v), layer t, source j), each summing all spindle x domain terms.  The
-// whole range [0, O^2 T n_src) runs the loops in the order of the plain sum.
-// mats and src are the shot's tables (global memory for the standalone
-// kernel, LDS for the served one); the arithmetic is the same in both, so a
-// shot gives the same bits through either path.  PF (tables in LDS): the next
-// spindle x domain matrix is read while the current term is evaluated, so the
-// LDS latency is hidden behind one term instead of stalling every term.
-template <int PREC, int SHAPE, bool CLAMP, bool PF = false>
-__device__ __forceinline__ double pixel_sum(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *mats,
-                                            const double *srcs, int i_f, int i_s, int q0, int q1)
-{
+// The running state of one pixel's sum over its outer iterations: binary64,
+// or for mixed sincg a Kahan-compensated binary32 sum (value s - c).  Carried
+// from one run of pixel_run to the next, it continues the sum exactly as one
+// uninterrupted run would.
+struct PixelAcc {
     double acc64 = 0.0;
     float acc = 0.0f, accc = 0.0f;
+};
+
+template <int PREC, int SHAPE>
+__device__ __forceinline__ double pixel_value(const PixelAcc &st)
+{
+    return PREC == XRT_MIXED && SHAPE == XRT_SHAPE_SINCG ? (double)(st.acc - st.accc) : st.acc64;
+}
+
+// The state as 8 bytes (binary64 sum, or the two binary32 words) and back.
+template <int PREC, int SHAPE>
+__device__ __forceinline__ uint64_t pixel_pack(const PixelAcc &st)
+{
+    if constexpr (PREC == XRT_MIXED && SHAPE == XRT_SHAPE_SINCG)
+        return (uint64_t)__builtin_bit_cast(uint32_t, st.acc) | ((uint64_t)__builtin_bit_cast(uint32_t, st.accc) << 32);
+    else
+        return __builtin_bit_cast(uint64_t, st.acc64);
+}
+
+template <int PREC, int SHAPE>
+__device__ __forceinline__ void pixel_unpack(PixelAcc &st, uint64_t v)
+{
+    if constexpr (PREC == XRT_MIXED && SHAPE == XRT_SHAPE_SINCG) {
+        st.acc = __builtin_bit_cast(float, (uint32_t)v);
+        st.accc = __builtin_bit_cast(float, (uint32_t)(v >> 32));
+    } else {
+        st.acc64 = __builtin_bit_cast(double, v);
+    }
+}
+
+// The per-pixel sum of pixel (i_f, i_s), not normalised, over the part
+// [q0, q1) of its outer iterations q = ((u O + v) T + t) n_src + j (sub-pixel
+// (u, v), layer t, source j), each summing all spindle x domain terms, added
+// into the running state st.  The whole range [0, O^2 T n_src) from a zero
+// state runs the loops in the order of the plain sum.  mats and src are the
+// shot's tables (global memory for the standalone kernel, LDS for the served
+// one); the arithmetic is the same in both, so a shot gives the same bits
+// through either path.  PF (tables in LDS): the next spindle x domain matrix
+// is read while the current term is evaluated, so the LDS latency is hidden
+// behind one term instead of stalling every term.
+template <int PREC, int SHAPE, bool CLAMP, bool PF = false>
+__device__ __forceinline__ void pixel_run(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *mats,
+                                          const double *srcs, int i_f, int i_s, int q0, int q1, PixelAcc &st)
+{
     const int per_t = p.T, per_v = p.O * p.T;
     int uvt = q0 / p.n_src, j0 = q0 - uvt * p.n_src;
     for (int q = q0; q < q1; ++uvt) {
@@ -544,14 +579,23 @@ __device__ __forceinline__ double pixel_sum(const Params &p, __amdgpu_buffer_rsr
             // binary64 outer sum, except for mixed sincg (Kahan binary32):
             // the mixed Gaussian sums leave the binary32 range
             if constexpr (PREC == XRT_MIXED && SHAPE == XRT_SHAPE_SINCG)
-                kahan_add(acc, accc, (float)w * (rs.s - rs.c));
+                kahan_add(st.acc, st.accc, (float)w * (rs.s - rs.c));
             else
-                acc64 = __builtin_fma(w, rs.value(), acc64);
+                st.acc64 = __builtin_fma(w, rs.value(), st.acc64);
         }
         q += j1 - j0;
         j0 = 0;
     }
-    return PREC == XRT_MIXED && SHAPE == XRT_SHAPE_SINCG ? (double)(acc - accc) : acc64;
+}
+
+// The sum over [q0, q1) from a zero state (pixel_run).
+template <int PREC, int SHAPE, bool CLAMP, bool PF = false>
+__device__ __forceinline__ double pixel_sum(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *mats,
+                                            const double *srcs, int i_f, int i_s, int q0, int q1)
+{
+    PixelAcc st;
+    pixel_run<PREC, SHAPE, CLAMP, PF>(p, tab, mats, srcs, i_f, i_s, q0, q1, st);
+    return pixel_value<PREC, SHAPE>(st);
 }
 
 // Part k of K of the outer iterations: [k n / K, (k + 1) n / K).
@@ -967,7 +1011,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PREC == X
     __shared__ double ssrc[SRC_STRIDE * SERVE_MAX_SRC];
     __shared__ long long s_claim;
     __shared__ uint64_t s_off, s_have_off;
-    __shared__ int32_t s_tile0, s_ntiles, s_kind;
+    __shared__ int32_t s_tile0, s_ntiles, s_kind, s_seg;
     __shared__ uint32_t s_seq1, s_shot, s_have_shot;  // s_have_*: the descriptor now in LDS
     const __amdgpu_buffer_rsrc_t tab = PREC == XRT_FP64 ? table_rsrc(a.F2_64, a.bytes64)
                                                          : table_rsrc(a.F2_32, a.bytes32);
@@ -1002,6 +1046,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PREC == X
                     s_seq1 = __hip_atomic_load(&ch->seq1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     s_shot = __hip_atomic_load(&ch->shot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     s_kind = __hip_atomic_load(&ch->kind, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    s_seg = __hip_atomic_load(&ch->seg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 } else if (__hip_atomic_load(&a.ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
                     c = -2;  // stop is honoured once nothing published is left
                 } else {
@@ -1069,6 +1114,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PREC == X
         const int n_units = uni(min(max(s_ntiles, 0), SERVE_MAX_CHUNK));
         const int tile0 = uni(s_tile0), kind = uni(s_kind);
         const int split = p.split;
+        const int n_seg = uni(max(sd.n_seg, 1)), seg = uni(min(max(s_seg, 0), n_seg - 1));
+        const uint64_t state = uni(sd.state_off), state_bytes = uni(sd.state_bytes);
         const int n_outer = p.O * p.O * p.T * p.n_src;
         const uint64_t img = uni(sd.image_off), part = uni(sd.partial_off);
         const uint64_t image_bytes = uni(sd.image_bytes), partial_bytes = uni(sd.partial_bytes);
@@ -1114,9 +1161,24 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PREC == X
             if (kind == CHUNK_COMPUTE) {
                 const int i_f = roi_f0 + (lf < p.roi_nf ? lf : p.roi_nf - 1);
                 const int i_s = roi_s0 + (ls < p.roi_ns ? ls : p.roi_ns - 1);
+                // segment seg of part k's outer iterations, continuing the
+                // running sum the previous segment left in the state slot
                 const int q0 = part_begin(k, split, n_outer), q1 = part_begin(k + 1, split, n_outer);
-                sum = clamp ? pixel_sum<PREC, SHAPE, true, true>(p, tab, smats, ssrc, i_f, i_s, q0, q1)
-                            : pixel_sum<PREC, SHAPE, false, true>(p, tab, smats, ssrc, i_f, i_s, q0, q1);
+                const int qa = q0 + part_begin(seg, n_seg, q1 - q0), qb = q0 + part_begin(seg + 1, n_seg, q1 - q0);
+                const uint64_t so = state + 8 * ((uint64_t)unit * BLOCK + ctid);
+                const bool state_ok = n_seg > 1 && state <= a.arena_bytes && so + 8 <= a.arena_bytes &&
+                                      8 * ((uint64_t)unit * BLOCK + BLOCK) <= state_bytes;
+                PixelAcc st;
+                if (seg > 0 && state_ok) pixel_unpack<PREC, SHAPE>(st, *reinterpret_cast<const uint64_t *>(a.arena + so));
+                if (clamp)
+                    pixel_run<PREC, SHAPE, true, true>(p, tab, smats, ssrc, i_f, i_s, qa, qb, st);
+                else
+                    pixel_run<PREC, SHAPE, false, true>(p, tab, smats, ssrc, i_f, i_s, qa, qb, st);
+                if (seg + 1 < n_seg) {
+                    if (state_ok) *reinterpret_cast<uint64_t *>(a.arena + so) = pixel_pack<PREC, SHAPE>(st);
+                    continue;
+                }
+                sum = pixel_value<PREC, SHAPE>(st);
                 if (split > 1) {
                     if (parts_ok) *reinterpret_cast<double *>(a.arena + pq + 8 * (uint64_t)k * BLOCK) = sum;
                     continue;

@@ -29,6 +29,26 @@ enum { QUEUED = 0, RUNNING = 1, DONE = 2 };
 
 inline uint64_t align_up(uint64_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
+// Default pixel-terms of one segment of a unit's sums (four standard chunks).
+constexpr uint64_t SEGMENT_TERMS = 4 * CHUNK_TERMS;
+
+// Segments of each work unit's outer iterations: a unit (a tile's sums, or
+// one part of split sums) heavier than segment_terms pixel-terms runs as K
+// consecutive segments of about equal length, the smallest K that keeps each
+// below segment_terms, at most the shortest part's outer-iteration count (so
+// no segment is empty).  A single tile-sized chunk otherwise holds its
+// workgroup for up to ~0.1 s (a tile of 2.4e5 terms per pixel), and a shot
+// that arrives meanwhile waits for workgroups to come free.
+inline int32_t segments_of(uint64_t terms_per_pixel, int32_t split, int64_t n_outer, uint64_t segment_terms)
+{
+    if (split < 1 || n_outer < 1 || segment_terms < 1) return 1;
+    const uint64_t per_unit = TILE_PIXELS * (terms_per_pixel / (uint64_t)split);
+    uint64_t k = (per_unit + segment_terms - 1) / segment_terms;
+    const uint64_t q_min = (uint64_t)(n_outer / split);
+    k = std::min<uint64_t>({k, std::max<uint64_t>(q_min, 1), (uint64_t)1 << 20});
+    return (int32_t)std::max<uint64_t>(k, 1);
+}
+
 // First-fit allocator over [0, size) with coalescing of freed neighbours.
 class Arena {
   public:
@@ -75,10 +95,11 @@ class Arena {
 // submission; the scheduler owns the rest.
 struct Work {
     uint64_t ticket = 0;
-    uint64_t footprint = 0;        // device arena bytes (image, then part sums)
+    uint64_t footprint = 0;        // device arena bytes (image, part sums, segment state)
     uint64_t desc_bytes = 0;       // host arena bytes (descriptor and tables)
     int32_t n_tiles = 0;           // 16 x 16 tiles of the region
     int32_t split = 1;             // parts per pixel sum (1: whole sums)
+    int32_t n_seg = 1;             // consecutive segments of each unit's outer iterations
     uint64_t terms_per_pixel = 0;
     uint64_t bg_terms_per_pixel = 0;  // > 0: a background phase over the tiles
                                       // once the image is complete
@@ -89,6 +110,7 @@ struct Work {
     // split sums, PHASE_REDUCE over tiles once every part is done, then, with
     // a background, PHASE_BACKGROUND over tiles once the image is complete
     int32_t phase = PHASE_COMPUTE;
+    int32_t seg = 0;               // PHASE_COMPUTE: the segment being published
     int32_t n_units = 0, chunk_units = 1, next_unit = 0;
     int64_t chunks_total = 0, chunks_done = 0;
     double work_published = 0;     // fair share: the shot's level (its start level plus
@@ -96,12 +118,14 @@ struct Work {
     double work_left = 0;          // pixel-terms of every phase not yet published
 };
 
-// One published chunk: units [unit0, unit0 + n_units) of a shot's phase.
+// One published chunk: units [unit0, unit0 + n_units) of a shot's phase
+// (and, for PHASE_COMPUTE, segment seg of their outer iterations).
 struct Chunk {
     uint64_t seq;                  // publication number
     uint64_t ticket;
-    int32_t kind;                  // PHASE_COMPUTE or PHASE_REDUCE
+    int32_t kind;                  // PHASE_COMPUTE, PHASE_REDUCE or PHASE_BACKGROUND
     int32_t unit0, n_units;
+    int32_t seg;
 };
 
 class Scheduler {
@@ -150,6 +174,7 @@ class Scheduler {
                 return st;
             }
             w.state = RUNNING;
+            w.seg = 0;
             start_phase(w, PHASE_COMPUTE);
             w.work_published = vtime_;  // it competes from now on, not from the start
             w.work_left = (double)w.n_tiles * TILE_PIXELS *
@@ -203,12 +228,13 @@ class Scheduler {
             c.seq = tail_++;
             c.ticket = w.ticket;
             c.kind = w.phase;
+            c.seg = w.phase == PHASE_COMPUTE ? w.seg : 0;
             c.unit0 = w.next_unit;
             c.n_units = std::min(w.chunk_units, w.n_units - w.next_unit);
             w.next_unit += c.n_units;
             // a reduce chunk reads K values per pixel: count it as K terms
             const double cw = (double)c.n_units * TILE_PIXELS *
-                              (w.phase == PHASE_COMPUTE  ? (double)w.terms_per_pixel / w.split
+                              (w.phase == PHASE_COMPUTE  ? (double)w.terms_per_pixel / w.split / w.n_seg
                                : w.phase == PHASE_REDUCE ? (double)w.split
                                                          : (double)w.bg_terms_per_pixel);
             w.work_published += cw;
@@ -223,7 +249,9 @@ class Scheduler {
     }
 
     // Finished chunks: is_done(seq) says whether chunk `seq` is done.  A
-    // compute phase of a split shot that completes starts its reduce phase;
+    // segment of the compute phase that completes starts the next segment
+    // (every unit's running sums of the last one are in the arena); the
+    // last segment of a split shot's compute phase starts its reduce phase;
     // the phase that completes the image starts the background phase of a
     // shot that has one; any other completed phase finishes the shot, whose
     // ticket is appended to *finished.
@@ -239,7 +267,11 @@ class Scheduler {
             }
             Work &w = work_[f.ticket];
             if (++w.chunks_done == w.chunks_total) {
-                if (w.phase == PHASE_COMPUTE && w.split > 1) {
+                if (w.phase == PHASE_COMPUTE && w.seg + 1 < w.n_seg) {
+                    w.seg++;
+                    start_phase(w, PHASE_COMPUTE);
+                    admitted_.push_back(w.ticket);
+                } else if (w.phase == PHASE_COMPUTE && w.split > 1) {
                     start_phase(w, PHASE_REDUCE);  // every part sum is in the arena
                     admitted_.push_back(w.ticket);
                 } else if (w.phase != PHASE_BACKGROUND && w.bg_terms_per_pixel > 0) {
@@ -318,7 +350,8 @@ class Scheduler {
         const uint64_t by_spread = ((uint64_t)w.n_units + n_wg_ - 1) / n_wg_;
         uint64_t by_cost = (uint64_t)MAX_CHUNK;
         if (phase != PHASE_REDUCE) {
-            const uint64_t tpp = phase == PHASE_COMPUTE ? w.terms_per_pixel / (uint64_t)w.split : w.bg_terms_per_pixel;
+            const uint64_t tpp = phase == PHASE_COMPUTE ? w.terms_per_pixel / (uint64_t)w.split / (uint64_t)w.n_seg
+                                                        : w.bg_terms_per_pixel;
             const uint64_t per_unit = std::max<uint64_t>(1, TILE_PIXELS * tpp);
             by_cost = std::max<uint64_t>(1, CHUNK_TERMS / per_unit);
         }

@@ -71,7 +71,7 @@ struct Shot {
     xrt_beam beam{};
     xrt_crystal xtal{};
     std::vector<double> dir, lam, weight, umats;
-    uint64_t image_bytes = 0, part_bytes = 0;
+    uint64_t image_bytes = 0, part_bytes = 0, state_bytes = 0;
     double t_submit = 0, t_admit = -1, t_done = -1;
     // write-out: the image's place in the host arena and the copy's event;
     // written once the copy has completed (the device memory is gone then)
@@ -141,6 +141,8 @@ xrt_status check_desc(const xrt_server_desc *d)
         return fail(XRT_ERANGE, "host_budget must be 0 or in [1 MiB, 1 TiB]");
     if (d->policy != XRT_SERVE_FAIR_SHARE && d->policy != XRT_SERVE_SHORTEST_REMAINING)
         return fail(XRT_EINVAL, "unknown policy %d", d->policy);
+    if (d->segment_terms != 0 && (d->segment_terms < (1 << 10) || d->segment_terms > ((int64_t)1 << 40)))
+        return fail(XRT_ERANGE, "segment_terms must be 0 or in [2^10, 2^40]");
     if (d->background) return xrt::host::check_background_desc(d->background);
     return XRT_OK;
 }
@@ -288,6 +290,9 @@ xrt_status admit(xrt_server *s)
         d.image_bytes = sh.image_bytes;
         d.partial_off = w.dev_off + align_up(sh.image_bytes);
         d.partial_bytes = sh.part_bytes;
+        d.n_seg = w.n_seg;
+        d.state_off = d.partial_off + align_up(sh.part_bytes);
+        d.state_bytes = sh.state_bytes;
         d.bg_norm = s->bg_knots ? xrt::host::background_norm(&sh.det, &sh.beam, s->bg_molecules) : 0.0;
         std::memcpy(s->host_arena + w.host_off, &d, sizeof d);
         std::memcpy(s->host_arena + w.host_off + d.mats_rel, host.data(), sizeof(double) * host.size());
@@ -308,7 +313,7 @@ void publish(xrt_server *s)
         c.seq1 = (uint32_t)(k.seq + 1);
         c.shot = (uint32_t)w.ticket ? (uint32_t)w.ticket : 1u;
         c.kind = k.kind;
-        c.pad = 0;
+        c.seg = k.seg;
     });
     if (n) __atomic_store_n(&s->ctrl->tail, s->sched->published(), __ATOMIC_RELEASE);
 }
@@ -473,7 +478,14 @@ xrt_status xrt_server_submit(xrt_server *s, const xrt_detector *det, const xrt_b
     if (s->bg_knots)  // the server's background, a phase after the sums
         w.bg_terms_per_pixel = (uint64_t)det->oversample * det->oversample * det->n_layers * (uint64_t)beam->n_src;
     sh.part_bytes = w.split > 1 ? sizeof(double) * (uint64_t)w.n_tiles * (uint64_t)w.split * xrt::sched::TILE_PIXELS : 0;
-    w.footprint = align_up(sh.image_bytes) + align_up(sh.part_bytes);
+    // heavy units run as consecutive segments, their running sums kept in
+    // the arena between two (8 bytes per unit and lane)
+    const int64_t n_outer = (int64_t)det->oversample * det->oversample * det->n_layers * beam->n_src;
+    w.n_seg = xrt::sched::segments_of(w.terms_per_pixel, w.split, n_outer,
+                                      s->desc.segment_terms ? (uint64_t)s->desc.segment_terms
+                                                            : xrt::sched::SEGMENT_TERMS);
+    sh.state_bytes = w.n_seg > 1 ? 8 * (uint64_t)w.n_tiles * (uint64_t)w.split * xrt::sched::TILE_PIXELS : 0;
+    w.footprint = align_up(sh.image_bytes) + align_up(sh.part_bytes) + align_up(sh.state_bytes);
     if (w.footprint > s->desc.hbm_budget)
         return fail(XRT_ERANGE, "shot needs %llu bytes, more than the server's budget %llu",
                     (unsigned long long)w.footprint, (unsigned long long)s->desc.hbm_budget);

@@ -80,7 +80,7 @@ class ServerDesc(C.Structure):
         ("struct_size", C.c_uint32), ("hbm_budget", C.c_uint64), ("max_resident", C.c_int32),
         ("precision", C.c_int32), ("shape", C.c_int32), ("out_dtype", C.c_int32),
         ("workgroups", C.c_int32), ("idle_exit_us", C.c_double), ("host_budget", C.c_uint64),
-        ("background", C.c_void_p), ("policy", C.c_int32),
+        ("background", C.c_void_p), ("policy", C.c_int32), ("segment_terms", C.c_int64),
     ]
 
 
@@ -442,11 +442,14 @@ class Server:
     progress() must be called often; image(ticket) returns a finished image as
     a torch tensor viewing the server's arena (copy it before release).
     policy: "shortest_remaining" (the next chunk from the shot with the least
-    work left) or "fair_share" (from the shot with the least work published)."""
+    work left) or "fair_share" (from the shot with the least work published).
+    segment_terms: the most pixel-terms of one tile's (or part's) sums a chunk
+    carries; heavier sums run as consecutive segments (0: the library's
+    default, 2^22)."""
 
     def __init__(self, fhkl: Fhkl, hbm_budget=8 << 30, max_resident=256, precision="mixed",
                  shape=XRT_SHAPE_SINCG, out_dtype=None, workgroups=0, idle_exit_us=5000.0, host_budget=0,
-                 background=None, policy="shortest_remaining"):
+                 background=None, policy="shortest_remaining", segment_terms=0):
         self.fhkl = fhkl  # kept alive: the server borrows its tables
         self.out_f64 = (out_dtype == "f64") if out_dtype else precision == "fp64"
         self.writes_out = bool(host_budget)
@@ -457,7 +460,8 @@ class Server:
                                 float(background.molecules))
         d = ServerDesc(C.sizeof(ServerDesc), int(hbm_budget), int(max_resident), _PREC[precision], int(shape),
                        XRT_F64 if self.out_f64 else XRT_F32, int(workgroups), float(idle_exit_us), int(host_budget),
-                       C.cast(C.pointer(bg), C.c_void_p) if bg is not None else None, _POLICY[policy])
+                       C.cast(C.pointer(bg), C.c_void_p) if bg is not None else None, _POLICY[policy],
+                       int(segment_terms))
         h = C.c_void_p()
         _check(load().xrt_server_create(C.byref(d), fhkl.handle, C.byref(h)))
         self._h = h

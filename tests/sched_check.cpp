@@ -26,9 +26,10 @@ using namespace xrt::sched;
     } while (0)
 
 static Work shot(uint64_t ticket, uint64_t footprint, int32_t n_tiles, uint64_t tpp, int32_t split = 1,
-                 uint64_t desc = 4096, uint64_t bg_tpp = 0)
+                 uint64_t desc = 4096, uint64_t bg_tpp = 0, int32_t n_seg = 1)
 {
     Work w;
+    w.n_seg = n_seg;
     w.bg_terms_per_pixel = bg_tpp;
     w.ticket = ticket;
     w.footprint = footprint;
@@ -55,6 +56,11 @@ struct Device {
             // a reduce chunk comes only after every compute chunk of its shot
             // is done, a background chunk only after every compute and reduce
             // chunk
+            // a compute chunk of segment k only after every compute chunk of
+            // its shot's earlier segments is done;
+            if (c.kind == PHASE_COMPUTE)
+                for (const Chunk &x : log)
+                    if (x.ticket == c.ticket && x.kind == PHASE_COMPUTE && x.seg < c.seg) CHECK(done.count(x.seq));
             if (c.kind == PHASE_REDUCE)
                 for (const Chunk &x : log)
                     if (x.ticket == c.ticket && x.kind == PHASE_COMPUTE) CHECK(done.count(x.seq));
@@ -170,7 +176,7 @@ static void check_fifo_admission()
 
 static void check_units_and_depth()
 {
-    printf("chunks: every unit of every phase exactly once, depth bound, phases in order\n");
+    printf("chunks: every unit of every phase (and segment) exactly once, depth bound, phases in order\n");
     Scheduler s(1 << 30, 1 << 22, 64, 16, 1 << 16);
     Device d(s);
     std::map<uint64_t, Work> shots;
@@ -180,7 +186,8 @@ static void check_units_and_depth()
         const uint64_t tpp = 1 + rng() % 200000;
         const int32_t split = (rng() % 3 == 0) ? 1 + (int32_t)(rng() % 64) : 1;
         const uint64_t bg = (rng() % 2 == 0) ? 1 + rng() % 2000 : 0;
-        shots[k] = shot(k, 4096, tiles, tpp, split, 4096, bg);
+        const int32_t n_seg = (rng() % 3 == 0) ? 1 + (int32_t)(rng() % 7) : 1;
+        shots[k] = shot(k, 4096, tiles, tpp, split, 4096, bg, n_seg);
         s.submit(shots[k]);
     }
     std::map<uint64_t, int> finished;
@@ -193,8 +200,10 @@ static void check_units_and_depth()
     }
     CHECK(finished.size() == shots.size());
     for (auto &f : finished) CHECK(f.second == 1);
-    // coverage per (shot, phase)
+    // coverage per (shot, phase); compute chunks once per segment, the
+    // segments of a shot in order
     std::map<std::pair<uint64_t, int>, std::vector<int>> cover;
+    std::map<uint64_t, int> seg_seen;
     std::map<uint64_t, uint64_t> last_compute, first_reduce, last_sums, first_bg;
     for (const Chunk &c : d.log) {
         auto &v = cover[{c.ticket, c.kind}];
@@ -205,12 +214,20 @@ static void check_units_and_depth()
         if (v.empty()) v.assign(n, 0);
         CHECK(c.n_units >= 1 && c.n_units <= MAX_CHUNK && c.unit0 >= 0 && c.unit0 + c.n_units <= n);
         for (int u = c.unit0; u < c.unit0 + c.n_units; ++u) v[u]++;
+        if (c.kind == PHASE_COMPUTE) {
+            CHECK(c.seg >= 0 && c.seg < w.n_seg && c.seg >= seg_seen[c.ticket]);
+            seg_seen[c.ticket] = c.seg;
+        } else {
+            CHECK(c.seg == 0);
+        }
         if (c.kind == PHASE_COMPUTE) last_compute[c.ticket] = std::max(last_compute[c.ticket], c.seq);
         if (c.kind == PHASE_REDUCE && !first_reduce.count(c.ticket)) first_reduce[c.ticket] = c.seq;
     }
     for (auto &kv : shots) {
         const Work &w = kv.second;
-        for (int x : cover[{w.ticket, PHASE_COMPUTE}]) CHECK(x == 1);
+        for (int x : cover[{w.ticket, PHASE_COMPUTE}]) CHECK(x == w.n_seg);
+        CHECK(seg_seen[w.ticket] == w.n_seg - 1);
+        CHECK(std::abs(s.find(w.ticket)->work_left) < 1.0);
         if (w.split > 1) {
             CHECK(cover.count({w.ticket, PHASE_REDUCE}));
             for (int x : cover[{w.ticket, PHASE_REDUCE}]) CHECK(x == 1);
@@ -457,9 +474,38 @@ static void check_ring_slot_reuse()
     CHECK(s.find(1)->state == DONE);
 }
 
+// The segment rule: the fewest segments that keep a unit's pixel-terms
+// within the budget, at most the shortest part's outer iterations.
+static void check_segments_of()
+{
+    printf("segments: count from the unit's pixel-terms, bounded by its outer iterations\n");
+    CHECK(segments_of(100, 1, 1200, SEGMENT_TERMS) == 1);                  // 25600 pixel-terms
+    CHECK(segments_of(240000, 1, 1200, SEGMENT_TERMS) == 15);              // 6.1e7 / 4.2e6 -> 14.6
+    CHECK(segments_of(240000, 2, 1200, SEGMENT_TERMS) == 8);               // half per part
+    CHECK(segments_of(16384, 1, 1200, SEGMENT_TERMS) == 1);                // exactly the budget
+    CHECK(segments_of(16385, 1, 1200, SEGMENT_TERMS) == 2);
+    CHECK(segments_of(240000, 1, 12, SEGMENT_TERMS) == 12);                // one outer iteration each
+    CHECK(segments_of(240000, 5, 12, SEGMENT_TERMS) == 2);                 // parts of 2 or 3 iterations
+    CHECK(segments_of(240000, 1, 1200, 1 << 10) == 1200);
+    CHECK(segments_of(0, 1, 1, SEGMENT_TERMS) == 1);
+    for (uint64_t tpp : {1ull, 977ull, 60000ull, 240000ull, 6553600ull})
+        for (int32_t split : {1, 3, 64})
+            for (int64_t n_outer : {64ll, 1200ll, 51200ll}) {
+                if (split > n_outer) continue;
+                const int32_t k = segments_of(tpp, split, n_outer, SEGMENT_TERMS);
+                const uint64_t per_unit = TILE_PIXELS * (tpp / split);
+                CHECK(k >= 1 && k <= n_outer / split);
+                // within the budget, unless the outer iterations ran out;
+                // and no fewer would do
+                CHECK((per_unit + k - 1) / k <= SEGMENT_TERMS || k == n_outer / split);
+                CHECK(k == 1 || (per_unit + k - 2) / (k - 1) > SEGMENT_TERMS);
+            }
+}
+
 int main()
 {
     check_arena();
+    check_segments_of();
     check_fifo_admission();
     check_units_and_depth();
     check_fair_share();

@@ -263,6 +263,21 @@ def test_server_desc_host_budget_range():
         assert "host_budget" in err()
 
 
+def test_server_desc_segment_terms_range():
+    """The segment size of served sums is validated before any device work:
+    0 (the default) or [2^10, 2^40]; the descriptor's size names the field."""
+    lib = xrt.load()
+    h = C.c_void_p()
+    for terms in (-1, 1, (1 << 10) - 1, (1 << 40) + 1):
+        d = xrt.ServerDesc(C.sizeof(xrt.ServerDesc), 1 << 30, 8, xrt.XRT_MIXED, xrt.XRT_SHAPE_SINCG, xrt.XRT_F32,
+                           0, 5000.0, 0, None, xrt.XRT_SERVE_SHORTEST_REMAINING, terms)
+        assert lib.xrt_server_create(C.byref(d), C.c_void_p(8), C.byref(h)) == xrt.XRT_ERANGE
+        assert "segment_terms" in err()
+    d = xrt.ServerDesc(C.sizeof(xrt.ServerDesc) - 8, 1 << 30, 8, xrt.XRT_MIXED, xrt.XRT_SHAPE_SINCG, xrt.XRT_F32,
+                       0, 5000.0, 0, None, xrt.XRT_SERVE_SHORTEST_REMAINING, 0)
+    assert lib.xrt_server_create(C.byref(d), C.c_void_p(8), C.byref(h)) == xrt.XRT_EVERSION
+
+
 def test_binding_fails_loudly_without_the_library(tmp_path):
     """With libxrt.so absent the binding raises instead of falling back to
     anything else (there is no CPU path in the product)."""

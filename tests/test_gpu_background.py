@@ -149,8 +149,10 @@ def test_served_with_background(precision):
         r = xrt.simulate(s, fh, precision=precision)
         xrt.simulate_background(s, water, precision=precision, out=r, accumulate=True)
         refs.append(r)
-    for host_budget in (0, 64 << 20):
-        srv = xrt.Server(fh, hbm_budget=256 << 20, precision=precision, host_budget=host_budget, background=water)
+    # read in place, written out, and with the sums run in segments
+    for host_budget, seg_terms in ((0, 0), (64 << 20, 0), (64 << 20, 1 << 12)):
+        srv = xrt.Server(fh, hbm_budget=256 << 20, precision=precision, host_budget=host_budget, background=water,
+                         segment_terms=seg_terms)
         tickets = [srv.submit(s) for s in shots]
         drain(srv, tickets)
         for i, t in enumerate(tickets):

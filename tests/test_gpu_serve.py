@@ -286,6 +286,49 @@ def expected_split(shot):
     return max(1, min(-(-2048 // tiles), n_outer, n_outer * shot.n_phi * shot.n_mos // 1024, 64))
 
 
+def expected_segments(shot, segment_terms):
+    """Segments of each unit's outer iterations (xrt_server_desc.segment_terms):
+    the fewest that keep a unit's pixel-terms within the budget, at most the
+    shortest part's outer iterations."""
+    split = expected_split(shot)
+    n_outer = shot.oversample ** 2 * shot.n_layers * shot.n_src
+    per_unit = 256 * (shot.terms_per_pixel // split)
+    return max(1, min(-(-per_unit // segment_terms), n_outer // split))
+
+
+@pytest.mark.parametrize("precision,shape", [("mixed", synth.SHAPE_SINCG), ("fp64", synth.SHAPE_SINCG),
+                                             ("mixed", synth.SHAPE_GAUSS), ("fp64", synth.SHAPE_GAUSS)])
+def test_segmented_sums_bitwise(precision, shape):
+    """Sums run as consecutive segments, each continuing the running sums the
+    previous one left in the arena (a small segment budget forces many, on
+    whole and on split sums): every image equals the standalone call's bit
+    for bit, in the mix and alone."""
+    seg_terms = 1 << 12
+    base, light = small_served_shots(4, seed=91)
+    _, heavy = heavy_small_shots(2, seed=94)
+    shots = light + heavy
+    if shape == synth.SHAPE_GAUSS:
+        rng = np.random.default_rng(93)
+        shots = [x.replace(shape=shape, N=rng.uniform(5.0, 40.0, 3)) for x in shots]
+    segs = [expected_segments(x, seg_terms) for x in shots]
+    splits = [expected_split(x) for x in shots]
+    say("segments", segs, "splits", splits)
+    assert min(segs) > 1 and any(k > 1 for k in splits)
+    fh = xrt.Fhkl.from_shot(base)
+    ref = [xrt.simulate(x, fh, precision=precision).cpu().numpy() for x in shots]
+    srv = xrt.Server(fh, hbm_budget=256 << 20, precision=precision, shape=shape, segment_terms=seg_terms)
+    tickets = [srv.submit(x) for x in shots]
+    drain(srv, tickets)
+    for i, t in enumerate(tickets):
+        assert np.array_equal(srv.image(t).cpu().numpy(), ref[i]), f"shot {i} ({segs[i]} segments) differs in the mix"
+        srv.release(t)
+    t = srv.submit(shots[-1])
+    drain(srv, [t])
+    assert np.array_equal(srv.image(t).cpu().numpy(), ref[-1]), "split shot differs alone"
+    srv.release(t)
+    srv.close()
+
+
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_served_split_shots(precision):
     """Split shots (part sums in the arena, reduce chunks after every part is
