@@ -110,9 +110,17 @@ struct Work {
     // split sums, PHASE_REDUCE over tiles once every part is done, then, with
     // a background, PHASE_BACKGROUND over tiles once the image is complete
     int32_t phase = PHASE_COMPUTE;
-    int32_t seg = 0;               // PHASE_COMPUTE: the segment being published
     int32_t n_units = 0, chunk_units = 1, next_unit = 0;
     int64_t chunks_total = 0, chunks_done = 0;
+    // PHASE_COMPUTE with segments: chunks whose units finished segment k and
+    // may run segment k + 1 (unit0, n_units, k + 1), published in that order
+    // once every unit has started (the units with the most segments left go
+    // first, so the phase ends with short chains, not with a few long ones)
+    struct Ready {
+        int32_t unit0, n_units, seg;
+    };
+    std::deque<Ready> ready;
+    bool listed = false;           // in the scheduler's list of shots with work to publish
     double work_published = 0;     // fair share: the shot's level (its start level plus
                                    // the pixel-terms of its chunks published since)
     double work_left = 0;          // pixel-terms of every phase not yet published
@@ -174,14 +182,13 @@ class Scheduler {
                 return st;
             }
             w.state = RUNNING;
-            w.seg = 0;
             start_phase(w, PHASE_COMPUTE);
             w.work_published = vtime_;  // it competes from now on, not from the start
             w.work_left = (double)w.n_tiles * TILE_PIXELS *
                           ((double)w.terms_per_pixel + (w.split > 1 ? (double)w.split : 0.0) +
                            (double)w.bg_terms_per_pixel);
             resident_++;
-            admitted_.push_back(w.ticket);
+            list(w);
             queue_.pop_front();
         }
         return 0;
@@ -228,10 +235,17 @@ class Scheduler {
             c.seq = tail_++;
             c.ticket = w.ticket;
             c.kind = w.phase;
-            c.seg = w.phase == PHASE_COMPUTE ? w.seg : 0;
-            c.unit0 = w.next_unit;
-            c.n_units = std::min(w.chunk_units, w.n_units - w.next_unit);
-            w.next_unit += c.n_units;
+            if (w.next_unit < w.n_units) {
+                c.seg = 0;
+                c.unit0 = w.next_unit;
+                c.n_units = std::min(w.chunk_units, w.n_units - w.next_unit);
+                w.next_unit += c.n_units;
+            } else {  // a later segment of units whose last one is done
+                c.unit0 = w.ready.front().unit0;
+                c.n_units = w.ready.front().n_units;
+                c.seg = w.ready.front().seg;
+                w.ready.pop_front();
+            }
             // a reduce chunk reads K values per pixel: count it as K terms
             const double cw = (double)c.n_units * TILE_PIXELS *
                               (w.phase == PHASE_COMPUTE  ? (double)w.terms_per_pixel / w.split / w.n_seg
@@ -239,19 +253,23 @@ class Scheduler {
                                                          : (double)w.bg_terms_per_pixel);
             w.work_published += cw;
             w.work_left -= cw;
-            inflight_.push_back({c.seq, c.ticket, cw});
+            inflight_.push_back({c.seq, c.ticket, cw, c.kind, c.unit0, c.n_units, c.seg});
             if (inflight_.size() > (size_t)n_wg_) waiting += cw;
             emit(c, w);
             ++n;
-            if (w.next_unit >= w.n_units) admitted_.erase(admitted_.begin() + best);
+            if (w.next_unit >= w.n_units && w.ready.empty()) {
+                w.listed = false;
+                admitted_.erase(admitted_.begin() + best);
+            }
         }
         return n;
     }
 
     // Finished chunks: is_done(seq) says whether chunk `seq` is done.  A
-    // segment of the compute phase that completes starts the next segment
-    // (every unit's running sums of the last one are in the arena); the
-    // last segment of a split shot's compute phase starts its reduce phase;
+    // compute chunk of segment k < n_seg - 1 makes its units ready for
+    // segment k + 1 (their running sums are in the arena); a compute phase
+    // whose every unit finished its last segment starts, for split sums, the
+    // reduce phase;
     // the phase that completes the image starts the background phase of a
     // shot that has one; any other completed phase finishes the shot, whose
     // ticket is appended to *finished.
@@ -266,17 +284,17 @@ class Scheduler {
                 continue;
             }
             Work &w = work_[f.ticket];
+            if (f.kind == PHASE_COMPUTE && f.seg + 1 < w.n_seg) {
+                w.ready.push_back({f.unit0, f.n_units, f.seg + 1});
+                list(w);
+            }
             if (++w.chunks_done == w.chunks_total) {
-                if (w.phase == PHASE_COMPUTE && w.seg + 1 < w.n_seg) {
-                    w.seg++;
-                    start_phase(w, PHASE_COMPUTE);
-                    admitted_.push_back(w.ticket);
-                } else if (w.phase == PHASE_COMPUTE && w.split > 1) {
+                if (w.phase == PHASE_COMPUTE && w.split > 1) {
                     start_phase(w, PHASE_REDUCE);  // every part sum is in the arena
-                    admitted_.push_back(w.ticket);
+                    list(w);
                 } else if (w.phase != PHASE_BACKGROUND && w.bg_terms_per_pixel > 0) {
                     start_phase(w, PHASE_BACKGROUND);  // the image is complete
-                    admitted_.push_back(w.ticket);
+                    list(w);
                 } else {
                     w.state = DONE;
                     if (finished) finished->push_back(w.ticket);
@@ -335,7 +353,17 @@ class Scheduler {
     struct InFlight {
         uint64_t seq, ticket;
         double work;  // pixel-terms
+        int32_t kind, unit0, n_units, seg;
     };
+
+    // Into the list of shots with work to publish (once).
+    void list(Work &w)
+    {
+        if (!w.listed) {
+            w.listed = true;
+            admitted_.push_back(w.ticket);
+        }
+    }
 
     // Chunking of a phase: compute and background chunks hold about
     // CHUNK_TERMS pixel-terms (a few ms of one workgroup, so a shot admitted
@@ -357,8 +385,11 @@ class Scheduler {
         }
         w.chunk_units = (int32_t)std::max<uint64_t>(1, std::min<uint64_t>({by_cost, by_spread, (uint64_t)MAX_CHUNK}));
         w.next_unit = 0;
-        w.chunks_total = (w.n_units + w.chunk_units - 1) / w.chunk_units;
+        // segments: every chunk's units run each segment once, in order
+        w.chunks_total = (int64_t)((w.n_units + w.chunk_units - 1) / w.chunk_units) *
+                         (phase == PHASE_COMPUTE ? std::max(w.n_seg, 1) : 1);
         w.chunks_done = 0;
+        w.ready.clear();
     }
 
     Arena dev_, host_;

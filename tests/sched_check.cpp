@@ -57,10 +57,12 @@ struct Device {
             // is done, a background chunk only after every compute and reduce
             // chunk
             // a compute chunk of segment k only after every compute chunk of
-            // its shot's earlier segments is done;
+            // an earlier segment over any of its units is done;
             if (c.kind == PHASE_COMPUTE)
                 for (const Chunk &x : log)
-                    if (x.ticket == c.ticket && x.kind == PHASE_COMPUTE && x.seg < c.seg) CHECK(done.count(x.seq));
+                    if (x.ticket == c.ticket && x.kind == PHASE_COMPUTE && x.seg < c.seg &&
+                        x.unit0 < c.unit0 + c.n_units && c.unit0 < x.unit0 + x.n_units)
+                        CHECK(done.count(x.seq));
             if (c.kind == PHASE_REDUCE)
                 for (const Chunk &x : log)
                     if (x.ticket == c.ticket && x.kind == PHASE_COMPUTE) CHECK(done.count(x.seq));
@@ -200,10 +202,10 @@ static void check_units_and_depth()
     }
     CHECK(finished.size() == shots.size());
     for (auto &f : finished) CHECK(f.second == 1);
-    // coverage per (shot, phase); compute chunks once per segment, the
-    // segments of a shot in order
+    // coverage per (shot, phase); compute units once per segment, each
+    // unit's segments in order
     std::map<std::pair<uint64_t, int>, std::vector<int>> cover;
-    std::map<uint64_t, int> seg_seen;
+    std::map<uint64_t, std::vector<int>> next_seg;  // per shot and compute unit
     std::map<uint64_t, uint64_t> last_compute, first_reduce, last_sums, first_bg;
     for (const Chunk &c : d.log) {
         auto &v = cover[{c.ticket, c.kind}];
@@ -215,8 +217,10 @@ static void check_units_and_depth()
         CHECK(c.n_units >= 1 && c.n_units <= MAX_CHUNK && c.unit0 >= 0 && c.unit0 + c.n_units <= n);
         for (int u = c.unit0; u < c.unit0 + c.n_units; ++u) v[u]++;
         if (c.kind == PHASE_COMPUTE) {
-            CHECK(c.seg >= 0 && c.seg < w.n_seg && c.seg >= seg_seen[c.ticket]);
-            seg_seen[c.ticket] = c.seg;
+            auto &ns = next_seg[c.ticket];
+            if (ns.empty()) ns.assign(n, 0);
+            CHECK(c.seg >= 0 && c.seg < w.n_seg);
+            for (int u = c.unit0; u < c.unit0 + c.n_units; ++u) CHECK(ns[u]++ == c.seg);
         } else {
             CHECK(c.seg == 0);
         }
@@ -226,7 +230,7 @@ static void check_units_and_depth()
     for (auto &kv : shots) {
         const Work &w = kv.second;
         for (int x : cover[{w.ticket, PHASE_COMPUTE}]) CHECK(x == w.n_seg);
-        CHECK(seg_seen[w.ticket] == w.n_seg - 1);
+        for (int x : next_seg[w.ticket]) CHECK(x == w.n_seg);
         CHECK(std::abs(s.find(w.ticket)->work_left) < 1.0);
         if (w.split > 1) {
             CHECK(cover.count({w.ticket, PHASE_REDUCE}));

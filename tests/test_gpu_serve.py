@@ -205,6 +205,39 @@ def test_refusals():
     srv.close()
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_served_at_the_limits(precision):
+    """A shot at the served limits (128 sources, 2 spindle steps x 128
+    domains = 256 matrices: the largest tables a workgroup stages in LDS),
+    on a ragged 23 x 19 region, beside a small one: bit for bit the
+    standalone images; one source or one matrix more is refused."""
+    base, shots = small_served_shots(2, seed=101)
+    rng = np.random.default_rng(102)
+    big = synth.served_shot(rng, base.F, base.hkl_min)
+    lam, w = synth.shots.gaussian_spectrum(rng, 128, 1.30, 0.003)
+    f0, s0 = 1200, 1250
+    big = big.replace(roi=(f0, f0 + 23, s0, s0 + 19), src_dir=synth.shots.on_axis_sources(128), src_lambda=lam,
+                      src_weight=w, umats=synth.shots.mosaic_umats(rng, 128, 0.05), n_phi=2, phi0=0.0, dphi=0.01)
+    assert big.n_src == 128 and big.n_phi * big.n_mos == 256
+    todo = [big, shots[0]]
+    fh = xrt.Fhkl.from_shot(base)
+    ref = [xrt.simulate(x, fh, precision=precision).cpu().numpy() for x in todo]
+    srv = xrt.Server(fh, hbm_budget=64 << 20, precision=precision)
+    tickets = [srv.submit(x) for x in todo]
+    drain(srv, tickets)
+    for i, t in enumerate(tickets):
+        assert np.array_equal(srv.image(t).cpu().numpy(), ref[i]), f"shot {i} differs"
+        srv.release(t)
+    more_src = big.replace(src_dir=synth.shots.on_axis_sources(129), src_lambda=np.full(129, 1.3),
+                           src_weight=np.full(129, 1.0 / 129))
+    more_rot = big.replace(umats=np.concatenate([big.umats, big.umats[:1]]))
+    for x in (more_src, more_rot):
+        with pytest.raises(xrt.XrtError) as e:
+            srv.submit(x)
+        assert e.value.code == xrt.XRT_ERANGE
+    srv.close()
+
+
 def test_relaunch_after_idle_exit():
     base, shots = small_served_shots(4, seed=9, max_side=48)
     fh = xrt.Fhkl.from_shot(base)
