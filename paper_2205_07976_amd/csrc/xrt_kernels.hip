@@ -350,6 +350,7 @@ __device__ __forceinline__ Pixel tile_pixel(const Params &p, int tile)
 template <int PREC, int SHAPE, bool CLAMP>
 struct RotSum {
     static constexpr bool KAHAN_SINCG = PREC == XRT_MIXED && SHAPE == XRT_SHAPE_SINCG;
+    static constexpr bool GAUSS64 = PREC == XRT_FP64 && SHAPE == XRT_SHAPE_GAUSS;
     double s64 = 0.0;
     float s = 0.0f, c = 0.0f;
     bool redo = false;  // mixed sincg: some term needs the floored ratio
@@ -447,6 +448,17 @@ __device__ __forceinline__ void rot_loop(const Params &p, __amdgpu_buffer_rsrc_t
         // copied back once per term
 #pragma unroll 2
         for (int r = 0; r < n; ++r) acc.template add<FLOORED>(p, tab, mats + 9 * r, S);
+    } else if constexpr (Acc::GAUSS64) {
+        // two terms per pass, written out (the exponential's inline asm keeps
+        // the compiler from unrolling): their Horner chains interleave
+        // instead of waiting out each other's dependent steps; the sum takes
+        // the terms in the same order
+        int r = 0;
+        for (; r + 1 < n; r += 2) {
+            acc.template add<FLOORED>(p, tab, mats + 9 * r, S);
+            acc.template add<FLOORED>(p, tab, mats + 9 * (r + 1), S);
+        }
+        if (r < n) acc.template add<FLOORED>(p, tab, mats + 9 * r, S);
     } else {
         for (int r = 0; r < n; ++r) acc.template add<FLOORED>(p, tab, mats + 9 * r, S);
     }
@@ -1399,8 +1411,12 @@ __global__ __launch_bounds__(BLOCK) void grad_kernel(const Params p, const void 
                     const double w = src[SRC_WEIGHT] * polarization(src, d, p.kahn) * wgeo;
                     if (PREC == XRT_FP64) {
                         const double e0 = vreg(p.ln_n2);
-                        for (int r = 0; r < p.n_rot; ++r)
+                        int r = 0;  // two terms per pass, as in rot_loop
+                        for (; r + 1 < p.n_rot; r += 2) {
                             grad_term_f64<CLAMP>(p, tab, p.qmats + 9 * r, S, w, acc, e0);
+                            grad_term_f64<CLAMP>(p, tab, p.qmats + 9 * (r + 1), S, w, acc, e0);
+                        }
+                        if (r < p.n_rot) grad_term_f64<CLAMP>(p, tab, p.qmats + 9 * r, S, w, acc, e0);
                     } else {
                         float a32[13];
 #pragma unroll
