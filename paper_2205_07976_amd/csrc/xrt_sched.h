@@ -145,7 +145,7 @@ class Scheduler {
               int policy = POLICY_FAIR_SHARE)
         : dev_(dev_bytes), host_(host_bytes), max_resident_(max_resident), n_wg_(std::max(n_wg, 1)),
           depth_(std::min<size_t>(ring - 1, 2 * (size_t)std::max(n_wg, 1))), ring_(ring),
-          slack_((double)std::max(n_wg, 1) * (double)CHUNK_TERMS), policy_(policy)
+          slack_(0.5 * (double)std::max(n_wg, 1) * (double)CHUNK_TERMS), policy_(policy)
     {
     }
 
@@ -198,12 +198,13 @@ class Scheduler {
     // sequence number stays within `ring` of the oldest chunk still in flight
     // (records and done flags live at seq % ring: a slow chunk must not share
     // its slot with a later one), and the chunks waiting for a workgroup hold
-    // less than `slack` pixel-terms (one standard chunk per workgroup, ~2 ms
-    // of the device: enough that no workgroup waits for the host between two
-    // progress calls, few enough that a chunk published now, which goes to
-    // the back of that queue, is not held back long; with two per workgroup
-    // the latency of served shots was 7-9 % higher at the median and 35-60 %
-    // higher in slowdown at p99, at the same capacity).  Workgroups claim chunks in publication order, so the
+    // less than `slack` pixel-terms (half a standard chunk per workgroup,
+    // ~1 ms of the device: enough that no workgroup waits for the host
+    // between two progress calls of a request loop that calls it often, few
+    // enough that a chunk published now, which goes to the back of that
+    // queue, is not held back long; with one or two per workgroup the
+    // latency of served shots was up to 7 % or 15 % higher at the median and
+    // up to 30 % or 2x higher in slowdown at p99, at the same capacity).  Workgroups claim chunks in publication order, so the
     // waiting ones are taken to be the in-flight chunks after the oldest
     // n_wg.  The next chunk comes, under POLICY_FAIR_SHARE, from the
     // admitted shot with the least work published so far (pixel-terms), so

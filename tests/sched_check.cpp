@@ -299,7 +299,7 @@ static void check_waiting_bound()
     const double big = 256.0 * 200000;  // one tile per chunk: 5.1e7 terms
     Scheduler s(1 << 30, 1 << 22, 8, n_wg, 1 << 16);
     Device d(s);
-    CHECK(s.slack() == (double)n_wg * CHUNK_TERMS && s.depth() == 2 * (size_t)n_wg);
+    CHECK(s.slack() == 0.5 * n_wg * CHUNK_TERMS && s.depth() == 2 * (size_t)n_wg);
     s.submit(shot(1, 4096, 100000, 200000));
     s.admit([](Work &) { return 0; });
     for (int it = 0; it < 50; ++it) {
