@@ -378,7 +378,7 @@ typedef struct xrt_server_desc {
                                chunk never holds a workgroup much longer than
                                this and a shot that arrives meanwhile waits
                                less for one; the images keep their bits.  0 =
-                               the default 2^22 (a few ms of one workgroup),
+                               the default 2^21 (a few ms of one workgroup),
                                else in [2^10, 2^40].  Segments need 8 bytes of
                                the device arena per pixel (per part) of a
                                segmented shot. */

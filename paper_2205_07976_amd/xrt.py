@@ -445,7 +445,7 @@ class Server:
     work left) or "fair_share" (from the shot with the least work published).
     segment_terms: the most pixel-terms of one tile's (or part's) sums a chunk
     carries; heavier sums run as consecutive segments (0: the library's
-    default, 2^22)."""
+    default, 2^21)."""
 
     def __init__(self, fhkl: Fhkl, hbm_budget=8 << 30, max_resident=256, precision="mixed",
                  shape=XRT_SHAPE_SINCG, out_dtype=None, workgroups=0, idle_exit_us=5000.0, host_budget=0,

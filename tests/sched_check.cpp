@@ -483,15 +483,18 @@ static void check_ring_slot_reuse()
 static void check_segments_of()
 {
     printf("segments: count from the unit's pixel-terms, bounded by its outer iterations\n");
-    CHECK(segments_of(100, 1, 1200, SEGMENT_TERMS) == 1);                  // 25600 pixel-terms
-    CHECK(segments_of(240000, 1, 1200, SEGMENT_TERMS) == 15);              // 6.1e7 / 4.2e6 -> 14.6
-    CHECK(segments_of(240000, 2, 1200, SEGMENT_TERMS) == 8);               // half per part
-    CHECK(segments_of(16384, 1, 1200, SEGMENT_TERMS) == 1);                // exactly the budget
-    CHECK(segments_of(16385, 1, 1200, SEGMENT_TERMS) == 2);
-    CHECK(segments_of(240000, 1, 12, SEGMENT_TERMS) == 12);                // one outer iteration each
-    CHECK(segments_of(240000, 5, 12, SEGMENT_TERMS) == 2);                 // parts of 2 or 3 iterations
+    CHECK(SEGMENT_TERMS == 2 * CHUNK_TERMS);
+    const uint64_t B = 4 * CHUNK_TERMS;  // a budget of 2^22 for the exact counts below
+    CHECK(segments_of(100, 1, 1200, B) == 1);                  // 25600 pixel-terms
+    CHECK(segments_of(240000, 1, 1200, B) == 15);              // 6.1e7 / 4.2e6 -> 14.6
+    CHECK(segments_of(240000, 2, 1200, B) == 8);               // half per part
+    CHECK(segments_of(16384, 1, 1200, B) == 1);                // exactly the budget
+    CHECK(segments_of(16385, 1, 1200, B) == 2);
+    CHECK(segments_of(240000, 1, 12, B) == 12);                // one outer iteration each
+    CHECK(segments_of(240000, 5, 12, B) == 2);                 // parts of 2 or 3 iterations
     CHECK(segments_of(240000, 1, 1200, 1 << 10) == 1200);
-    CHECK(segments_of(0, 1, 1, SEGMENT_TERMS) == 1);
+    CHECK(segments_of(0, 1, 1, B) == 1);
+    CHECK(segments_of(240000, 1, 1200, SEGMENT_TERMS) == 30);              // the default: 6.1e7 / 2.1e6
     for (uint64_t tpp : {1ull, 977ull, 60000ull, 240000ull, 6553600ull})
         for (int32_t split : {1, 3, 64})
             for (int64_t n_outer : {64ll, 1200ll, 51200ll}) {
