@@ -672,7 +672,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); shots would be sharded "
-              "one per GPU with no exchange, which this build does not launch.", file=sys.stderr)
+              "one per GPU with no exchange, and no multi-GPU launch is provided.", file=sys.stderr)
         return 2
     sections = set(args.only.split(",")) - {""} if args.only else set(DEFAULT_SECTIONS)
     unknown = sections - set(SECTIONS)
