@@ -206,6 +206,26 @@ def test_refusals():
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_full_shot_region_default_segments(precision):
+    """A 1024 x 512 region of the full-size shot (2048 tiles, whole sums;
+    100 sources, 50 domains, 60 000 terms per pixel) on a server with the
+    default segment size, where every tile's sum runs as several consecutive
+    segments: the image equals the standalone call's bit for bit."""
+    shot = synth.full_shot().replace(roi=(700, 1724, 1000, 1512))
+    segs = expected_segments(shot, 1 << 21)
+    say("full-shot region: segments per tile", segs)
+    assert segs > 1 and expected_split(shot) == 1
+    fh = xrt.Fhkl.from_shot(shot)
+    ref = xrt.simulate(shot, fh, precision=precision).cpu().numpy()
+    srv = xrt.Server(fh, hbm_budget=256 << 20, precision=precision)
+    t = srv.submit(shot)
+    drain(srv, [t])
+    assert np.array_equal(srv.image(t).cpu().numpy(), ref)
+    srv.release(t)
+    srv.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_served_at_the_limits(precision):
     """A shot at the served limits (128 sources, 2 spindle steps x 128
     domains = 256 matrices: the largest tables a workgroup stages in LDS),
