@@ -427,8 +427,12 @@ xrt_status xrt_server_submit(xrt_server *srv, const xrt_detector *det,
 
 /* Collect finished work, admit queued shots, publish chunks and (re)launch the
  * persistent kernel if it is not running; *n_done receives the number of
- * shots seen finishing during this call (may be NULL).  Errors: EINVAL (wrong
- * device), EDEVICE (the kernel or a launch failed). */
+ * shots seen finishing during this call (may be NULL).  The device is kept
+ * fed for about a millisecond ahead (every workgroup busy plus half a
+ * standard chunk of work per workgroup waiting; a segment's successor is
+ * published only once this call has seen it finish), so a request loop that
+ * calls it less often than that leaves workgroups idle.  Errors: EINVAL
+ * (wrong device), EDEVICE (the kernel or a launch failed). */
 xrt_status xrt_server_progress(xrt_server *srv, int32_t *n_done);
 
 /* State and times of a shot.  info->struct_size must be set. */
