@@ -474,7 +474,8 @@ xrt_status xrt_sinpi(const double *dev_x, int64_t n, double *dev_s64, float *dev
 
 /* Diagnostics: the binary64 kernels' exp(x) (the Gaussian lattice factor,
  * section II's crystal-size transform in its Gaussian form): reduction by
- * x = n ln2 + r, a polynomial for exp(r), scaling by 2^n; for x <= 709.
+ * x = (64 k + j) ln2/64 + r, a polynomial for exp(r), the product with a
+ * table entry 2^(j/64), scaling by 2^k; for x <= 709.
  * dev_x, dev_y: [n] binary64.  Enqueued on `stream`.
  * Errors: ERANGE (n < 0), EINVAL (NULL arrays), EDEVICE. */
 xrt_status xrt_exp(const double *dev_x, int64_t n, double *dev_y, void *stream);

@@ -1,12 +1,18 @@
-"""Minimax fit of exp(r) on |r| <= ln(2)/2 used by the binary64 Gaussian
-lattice factor.
+"""Minimax fits of exp(r) for the binary64 exponentials of xrt_math.h.
 
-exp(e) = 2^n exp(r) with n = rint(e / ln 2) and r = e - n ln 2 (Cody and
-Waite's reduction with ln 2 split into a binary64 head and tail); exp(r) is a
-polynomial P(r) minimising the maximum relative error on [-ln2/2, ln2/2],
-found by the Remez exchange algorithm in 50-digit mpmath, rounded to
-binary64 and re-checked on a dense grid.  Run as a script to print the
-coefficient table that xrt_math.h carries.
+exp_f64 (the Gaussian lattice factor) uses Tang's table-driven reduction:
+e = (64 k + j) ln2/64 + r with j in [0, 64), exp(e) = 2^k 2^(j/64) exp(r) and
+|r| <= ln2/128; exp(r) is a degree-5 polynomial there.  expm1_f64 uses
+e = n ln2 + r, |r| <= ln2/2, and a degree-11 polynomial.  Both reductions
+split the constant (ln2/64, ln2) into a binary64 head and tail (Cody and
+Waite).  Each polynomial P(r) minimises the maximum relative error on its
+interval, found by the Remez exchange algorithm in 50-digit mpmath, rounded
+to binary64 and re-checked on a dense grid.  Run as a script to print the
+coefficients, the reduction constants and the table of 2^(j/64), each
+rounded to nearest binary64, that xrt_math.h carries:
+
+    python fit_exp.py 11 1    # expm1_f64: degree 11 on |r| <= ln2/2
+    python fit_exp.py 5 64    # exp_f64: degree 5 on |r| <= ln2/128, table
 """
 from __future__ import annotations
 
@@ -70,11 +76,17 @@ def max_rel_err(coeffs, n=20001):
 
 if __name__ == "__main__":
     deg = int(sys.argv[1]) if len(sys.argv) > 1 else 11
+    steps = int(sys.argv[2]) if len(sys.argv) > 2 else 1  # table entries per octave
+    R1 = mp.log(2) / (2 * steps)
     c, E = remez(deg)
     print(f"degree {deg}: minimax relative error {mp.nstr(E, 4)}, "
           f"after rounding {mp.nstr(max_rel_err(c), 4)}")
     for k in range(deg, -1, -1):
         print(f"  c{k} = {float(c[k])!r}")
-    ln2 = mp.log(2)
+    ln2 = mp.log(2) / steps
     hi = float(ln2)
-    print(f"ln2 head {hi!r}, tail {float(ln2 - mp.mpf(hi))!r}, 1/ln2 {float(1 / ln2)!r}")
+    print(f"ln2/{steps} head {hi!r}, tail {float(ln2 - mp.mpf(hi))!r}, {steps}/ln2 {float(1 / ln2)!r}")
+    if steps > 1:
+        tab = [float(mp.power(2, mp.mpf(j) / steps)) for j in range(steps)]
+        for j in range(0, steps, 4):
+            print("    " + " ".join(f"{x.hex()}," for x in tab[j:j + 4]))

@@ -68,7 +68,7 @@ __device__ __forceinline__ double sample_weight(const Params &p, const double d[
     const double domega = p.pixel * p.pixel * cosrho / (R * R);
     if (p.layer_dt == 0.0) return domega;
     const double l = p.atten_len * cosrho;
-    return domega * exp_f64(-(double)t * p.layer_dt / l) * -expm1_f64(-p.layer_dt / l);
+    return domega * exp_cw_f64(-(double)t * p.layer_dt / l) * -expm1_f64(-p.layer_dt / l);
 }
 
 // S = (d - dir_j) / lambda_j, binary64.
@@ -192,7 +192,8 @@ __device__ __forceinline__ double recip_newton(double d)
 // ---------------------------------------------------------------------------
 template <int SHAPE, bool CLAMP, bool FLOORED>
 __device__ __forceinline__ double term_f64_add(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3],
-                                               double s, double c6 = SINPI_C6, double e0 = 0.0)
+                                               double s, double c6 = SINPI_C6, double e0 = 0.0,
+                                               double c5 = EXP_C5)
 {
     double hr[3];
     if (SHAPE == XRT_SHAPE_SINCG) {
@@ -218,7 +219,7 @@ __device__ __forceinline__ double term_f64_add(const Params &p, __amdgpu_buffer_
             e = __builtin_fma(-p.gk[i], f * f, e);
         }
         const double F2 = load_f64(tab, table_offset<CLAMP>(p, hr, p.off64));
-        return __builtin_fma(F2, exp_f64(e), s);
+        return __builtin_fma(F2, exp_f64(e, c5), s);
     }
 }
 
@@ -355,6 +356,7 @@ struct RotSum {
     float s = 0.0f, c = 0.0f;
     bool redo = false;  // mixed sincg: some term needs the floored ratio
     double c6 = SINPI_C6;  // binary64 sincg: sinpi_over_x's c6, set by rot_loop
+    double c5 = EXP_C5;    // binary64 Gaussian: exp_f64's c5, set by rot_loop
     double e0 = 0.0;       // Gaussian: ln(Na^2 Nb^2 Nc^2), set by the term loops
     GaussRef ref;  // mixed Gaussian: reference exponent
     // h = M S by the sequence of this precision
@@ -377,7 +379,7 @@ struct RotSum {
     __device__ __forceinline__ void add_h(const Params &p, __amdgpu_buffer_rsrc_t tab, const double h[3])
     {
         if constexpr (PREC == XRT_FP64) {
-            s64 = term_f64_add<SHAPE, CLAMP, FLOORED>(p, tab, h, s64, c6, e0);
+            s64 = term_f64_add<SHAPE, CLAMP, FLOORED>(p, tab, h, s64, c6, e0, c5);
         } else if constexpr (SHAPE == XRT_SHAPE_SINCG) {
             bool ok;
             kahan_add(s, c, term_mixed_sincg<CLAMP, FLOORED>(p, tab, h, ok));
@@ -433,6 +435,7 @@ __device__ __forceinline__ void rot_loop(const Params &p, __amdgpu_buffer_rsrc_t
 {
     const int n = p.n_rot;
     acc.c6 = vreg(SINPI_C6);
+    acc.c5 = vreg(EXP_C5);
     acc.e0 = vreg(p.ln_n2);
     if (PF) {
         double m[9];
@@ -1269,7 +1272,8 @@ hipError_t launch_serve(const ServeArgs &a, int precision, int shape, int n_wg, 
 // ---------------------------------------------------------------------------
 template <bool CLAMP>
 __device__ __forceinline__ void grad_term_f64(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *Q,
-                                              const double S[3], double w, double acc[13], double e0)
+                                              const double S[3], double w, double acc[13], double e0,
+                                              double c5)
 {
     double Sp[3], hr[3], f[3];
 #pragma unroll
@@ -1282,7 +1286,7 @@ __device__ __forceinline__ void grad_term_f64(const Params &p, __amdgpu_buffer_r
         f[i] = h - hr[i];
         e = __builtin_fma(-p.gk[i], f[i] * f[i], e);
     }
-    const double base = w * load_f64(tab, table_offset<CLAMP>(p, hr, p.off64)) * exp_f64(e);
+    const double base = w * load_f64(tab, table_offset<CLAMP>(p, hr, p.off64)) * exp_f64(e, c5);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const double dh = base * p.m2gk[i] * f[i];
@@ -1410,13 +1414,13 @@ __global__ __launch_bounds__(BLOCK) void grad_kernel(const Params p, const void 
                     scatter(src, d, S);
                     const double w = src[SRC_WEIGHT] * polarization(src, d, p.kahn) * wgeo;
                     if (PREC == XRT_FP64) {
-                        const double e0 = vreg(p.ln_n2);
+                        const double e0 = vreg(p.ln_n2), c5 = vreg(EXP_C5);
                         int r = 0;  // two terms per pass, as in rot_loop
                         for (; r + 1 < p.n_rot; r += 2) {
-                            grad_term_f64<CLAMP>(p, tab, p.qmats + 9 * r, S, w, acc, e0);
-                            grad_term_f64<CLAMP>(p, tab, p.qmats + 9 * (r + 1), S, w, acc, e0);
+                            grad_term_f64<CLAMP>(p, tab, p.qmats + 9 * r, S, w, acc, e0, c5);
+                            grad_term_f64<CLAMP>(p, tab, p.qmats + 9 * (r + 1), S, w, acc, e0, c5);
                         }
-                        if (r < p.n_rot) grad_term_f64<CLAMP>(p, tab, p.qmats + 9 * r, S, w, acc, e0);
+                        if (r < p.n_rot) grad_term_f64<CLAMP>(p, tab, p.qmats + 9 * r, S, w, acc, e0, c5);
                     } else {
                         float a32[13];
 #pragma unroll

@@ -68,16 +68,17 @@ __device__ __forceinline__ float sinpi_over_x(float y)
     return p;
 }
 
-// exp(e) in binary64 for the Gaussian lattice factor: e = n ln2 + r with
-// n = rint(e / ln2) and r reduced by two fused multiply-adds against ln2 split
-// into a binary64 head and tail (Cody and Waite's reduction); exp(r) on
-// |r| <= ln2/2 is a degree-11 relative-minimax polynomial (fit_exp.py in this
+// e^x and e^x - 1 in binary64 for the layer capture, without a table (they
+// run once per sample point and layer, where the table's registers would
+// cost the term loops occupancy): x = n ln2 + r with n = rint(x / ln2) and r
+// reduced by two fused multiply-adds against ln2 split into a binary64 head
+// and tail (Cody and Waite's reduction); exp(r) on |r| <= ln2/2 is a
+// degree-11 relative-minimax polynomial 1 + r q(r) (fit_exp.py in this
 // directory: 2.3e-17 with the coefficients as stored), evaluated by Horner's
 // rule with fused multiply-adds; 2^n is applied by ldexp, which also yields
 // the subnormal results and 0 below the binary64 range.  The Horner steps
-// with coefficients other than 1 use fma_sc.  For e <= 709 (the
-// lattice exponents are at most log(Na^2 Nb^2 Nc^2)); e is raised to -1100
-// first, where the result is 0 either way, so n fits an int.
+// with coefficients other than 1 use fma_sc.  x is raised to -1100 first,
+// where the results are 0 and -1 either way, so n fits an int.  For x <= 709.
 __device__ __forceinline__ double exp_q(double r)  // e^r = 1 + r q(r) on |r| <= ln2/2
 {
     double p = 2.4994304884817207e-08;
@@ -102,23 +103,80 @@ __device__ __forceinline__ double exp_reduce(double &e, double &n)
     return __builtin_fma(-n, 2.3190468138462996e-17, r);
 }
 
-__device__ __forceinline__ double exp_f64(double e)
+__device__ __forceinline__ double exp_cw_f64(double x)
 {
     double n;
-    const double r = exp_reduce(e, n);
+    const double r = exp_reduce(x, n);
     return __builtin_ldexp(__builtin_fma(exp_q(r), r, 1.0), (int)n);
 }
 
-// e^x - 1 in binary64 with the same reduction and polynomial: r q(r) when
-// n = 0 (|x| <= ln2/2, where e^x - 1 would cancel), otherwise
-// 2^n (1 + r q(r)) - 1, whose subtraction loses at most a bit or two (for
-// n = -1 the difference is at least 1 - e^(-ln2/2) = 0.29).  For x <= 709.
+// e^x - 1: r q(r) when n = 0 (|x| <= ln2/2, where e^x - 1 would cancel),
+// otherwise 2^n (1 + r q(r)) - 1, whose subtraction loses at most a bit or
+// two (for n = -1 the difference is at least 1 - e^(-ln2/2) = 0.29).
 __device__ __forceinline__ double expm1_f64(double x)
 {
     double n;
     const double r = exp_reduce(x, n);
     const double q = exp_q(r);
     return n == 0.0 ? r * q : __builtin_ldexp(__builtin_fma(q, r, 1.0), (int)n) - 1.0;
+}
+
+// 2^(j/64), j = 0..63, each rounded to nearest binary64 (fit_exp.py prints them).
+__device__ const double EXP2_J64[64] = {
+    0x1.0000000000000p+0, 0x1.02c9a3e778061p+0, 0x1.059b0d3158574p+0, 0x1.0874518759bc8p+0,
+    0x1.0b5586cf9890fp+0, 0x1.0e3ec32d3d1a2p+0, 0x1.11301d0125b51p+0, 0x1.1429aaea92de0p+0,
+    0x1.172b83c7d517bp+0, 0x1.1a35beb6fcb75p+0, 0x1.1d4873168b9aap+0, 0x1.2063b88628cd6p+0,
+    0x1.2387a6e756238p+0, 0x1.26b4565e27cddp+0, 0x1.29e9df51fdee1p+0, 0x1.2d285a6e4030bp+0,
+    0x1.306fe0a31b715p+0, 0x1.33c08b26416ffp+0, 0x1.371a7373aa9cbp+0, 0x1.3a7db34e59ff7p+0,
+    0x1.3dea64c123422p+0, 0x1.4160a21f72e2ap+0, 0x1.44e086061892dp+0, 0x1.486a2b5c13cd0p+0,
+    0x1.4bfdad5362a27p+0, 0x1.4f9b2769d2ca7p+0, 0x1.5342b569d4f82p+0, 0x1.56f4736b527dap+0,
+    0x1.5ab07dd485429p+0, 0x1.5e76f15ad2148p+0, 0x1.6247eb03a5585p+0, 0x1.6623882552225p+0,
+    0x1.6a09e667f3bcdp+0, 0x1.6dfb23c651a2fp+0, 0x1.71f75e8ec5f74p+0, 0x1.75feb564267c9p+0,
+    0x1.7a11473eb0187p+0, 0x1.7e2f336cf4e62p+0, 0x1.82589994cce13p+0, 0x1.868d99b4492edp+0,
+    0x1.8ace5422aa0dbp+0, 0x1.8f1ae99157736p+0, 0x1.93737b0cdc5e5p+0, 0x1.97d829fde4e50p+0,
+    0x1.9c49182a3f090p+0, 0x1.a0c667b5de565p+0, 0x1.a5503b23e255dp+0, 0x1.a9e6b5579fdbfp+0,
+    0x1.ae89f995ad3adp+0, 0x1.b33a2b84f15fbp+0, 0x1.b7f76f2fb5e47p+0, 0x1.bcc1e904bc1d2p+0,
+    0x1.c199bdd85529cp+0, 0x1.c67f12e57d14bp+0, 0x1.cb720dcef9069p+0, 0x1.d072d4a07897cp+0,
+    0x1.d5818dcfba487p+0, 0x1.da9e603db3285p+0, 0x1.dfc97337b9b5fp+0, 0x1.e502ee78b3ff6p+0,
+    0x1.ea4afa2a490dap+0, 0x1.efa1bee615a27p+0, 0x1.f50765b6e4540p+0, 0x1.fa7c1819e90d8p+0,
+};
+
+// exp(e) in binary64 for the Gaussian lattice factor, by Tang's table-driven
+// method: e = n ln2/64 + r with n the integer nearest e 64/ln2, so that
+// exp(e) = 2^k 2^(j/64) exp(r) for n = 64 k + j, 0 <= j < 64, |r| <= ln2/128.
+// n comes from one fused multiply-add: e 64/ln2 + 1.5 2^52 rounds the exact
+// product to an integer, which the low word of the result holds in two's
+// complement, and subtracting 1.5 2^52 again gives n exactly.  r is reduced
+// by two fused multiply-adds against ln2/64 split into a binary64 head and
+// tail (Cody and Waite); exp(r) = 1 + r q(r) with q of degree 4 (a degree-5
+// relative-minimax polynomial, fit_exp.py: 2.2e-18 with the coefficients as
+// stored), and the result 2^(j/64) + 2^(j/64) r q(r) is formed by one fused
+// multiply-add and scaled by ldexp, which also yields the subnormal results
+// and 0 below the binary64 range.  Error: half an ulp from the table entry,
+// half from the last rounding, a few hundredths from the rest.  For e <= 709
+// (the lattice exponents are at most log(Na^2 Nb^2 Nc^2)); e is raised to
+// -1100 first, where the result is 0 either way, so |n| stays below 2^17.
+// The leading coefficient of exp_f64's polynomial.  A loop that evaluates
+// many exponentials passes a copy that the compiler cannot see through (the
+// first Horner step's other constant takes the one scalar operand), as with
+// SINPI_C6.
+constexpr double EXP_C5 = 0.008333324607332198;
+
+__device__ __forceinline__ double exp_f64(double e, double c5 = EXP_C5)
+{
+    constexpr double SHIFT = 0x1.8p52;
+    e = __builtin_fmax(e, -1100.0);
+    const double t = __builtin_fma(e, 92.33248261689366, SHIFT);
+    const double n = t - SHIFT;
+    const int ni = (int)(uint32_t)__builtin_bit_cast(uint64_t, t);
+    double r = __builtin_fma(-n, 0.010830424696249145, e);
+    r = __builtin_fma(-n, 3.623510646634843e-19, r);
+    const double T = EXP2_J64[ni & 63];
+    double q = fma_sc(c5, r, 0.04166672775933016);
+    q = fma_sc(q, r, 0.16666666666721047);
+    q = fma_sc(q, r, 0.4999999999993282);
+    q = __builtin_fma(q, r, 1.0);
+    return __builtin_ldexp(__builtin_fma(T, r * q, T), ni >> 6);
 }
 
 // sin(pi x) for |x| <= 1/2, composed as the lattice factor uses it.

@@ -100,9 +100,10 @@ def test_exp_binary64_against_extended_precision():
     """The binary64 kernels' exp (Gaussian lattice factor) against 80-bit host
     exp on 2^21 seeded points of [-760, 45] (the lattice exponents lie in
     (-inf, log(Na^2 Nb^2 Nc^2)]), including the subnormal range and exact 0
-    below it.  Bound: 2 ulp (fit 0.2 ulp + Horner and reduction roundings);
-    a subnormal result is that value rounded once more to the subnormal grid:
-    2 ulp of the unrounded value (at most 2 spacings) + half a spacing."""
+    below it.  Bound: 2 ulp (the table entry's rounding and the last one,
+    half an ulp each, the fit 0.01 ulp, the reduction less); a subnormal
+    result is that value rounded once more to the subnormal grid: 2 ulp of
+    the unrounded value (at most 2 spacings) + half a spacing."""
     assert np.finfo(np.longdouble).nmant >= 63, "needs 80-bit long double on the host"
     rng = np.random.default_rng(12)
     x = np.concatenate([rng.uniform(-760.0, 45.0, 1 << 21), rng.uniform(-2.0, 2.0, 1 << 16),

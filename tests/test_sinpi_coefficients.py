@@ -1,9 +1,11 @@
-"""The sin(pi x) and exp polynomials the kernels carry (paper_2205_07976_amd/csrc/
-xrt_math.h), checked on the CPU against 50-digit mpmath: the coefficients as
-stored, evaluated exactly, stay within the relative error the header states
-(binary64 2.2e-16, binary32 4.3e-8) over a dense grid of [0, 1/2].  The
-polynomial carries the lattice factor's sin(pi f) and sin(pi g) (the
-crystal-size transform of paper section II)."""
+"""The sin(pi x) and exp polynomials and the exp table the kernels carry
+(paper_2205_07976_amd/csrc/xrt_math.h), checked on the CPU against 50-digit
+mpmath: the coefficients as stored, evaluated exactly, stay within the
+relative error the header states (sin: binary64 2.2e-16, binary32 4.3e-8 over
+a dense grid of [0, 1/2]); the table entries and reduction constants are the
+correctly rounded binary64 values.  The sine carries the lattice factor's
+sin(pi f) and sin(pi g), the exp its Gaussian form (the crystal-size
+transform of paper section II) and the layer capture."""
 import os
 import re
 
@@ -51,7 +53,7 @@ def test_stored_polynomial_error(kind, bound, degree):
 
 def exp_coefficients():
     """Horner coefficients of exp(r) = 1 + r q(r), highest degree first: those
-    of exp_q, then the final 1 that exp_f64 adds."""
+    of exp_q, then the final 1 that exp_cw_f64 adds."""
     src = open(HEADER).read()
     body = src[src.index("double exp_q(double r)"):]
     body = body[body.index("double p = "):body.index("}")]
@@ -59,9 +61,9 @@ def exp_coefficients():
 
 
 def test_stored_exp_polynomial_error():
-    """exp(r) on |r| <= ln2/2 (the reduced argument of the binary64 Gaussian
-    lattice factor): the stored degree-11 polynomial, evaluated exactly, stays
-    within 2.3e-17 relative of 50-digit exp."""
+    """exp(r) on |r| <= ln2/2 (the reduced argument of the capture's exp and
+    expm1): the stored degree-11 polynomial, evaluated exactly, stays within
+    2.3e-17 relative of 50-digit exp."""
     mp.mp.dps = 50
     cs = exp_coefficients()
     assert len(cs) == 12 and cs[-1] == 1 and cs[-2] == 1
@@ -75,3 +77,54 @@ def test_stored_exp_polynomial_error():
             p = p * x + c
         worst = max(worst, abs(p / mp.exp(x) - 1))
     assert worst <= 2.3e-17, float(worst)
+
+
+def exp_f64_source():
+    src = open(HEADER).read()
+    body = src[src.index("double exp_f64(double e, double c5"):]
+    return src, body[:body.index("\n}")]
+
+
+def test_table_exp_polynomial_error():
+    """exp(r) on |r| <= ln2/128 (the reduced argument of the Gaussian lattice
+    factor's table-driven exp): 1 + r q(r) with q's coefficients as stored
+    (the named EXP_C5, then the three of the Horner steps, then 1), evaluated
+    exactly, stays within 2.3e-18 relative of 50-digit exp."""
+    mp.mp.dps = 50
+    src, body = exp_f64_source()
+    c5 = re.search(r"constexpr double EXP_C5 = ([-+]?\d+\.\d+(?:e[-+]?\d+)?);", src).group(1)
+    steps = re.findall(r"fma_sc\(c5, r, ([-+]?\d+\.\d+(?:e[-+]?\d+)?)\)|fma_sc\(q, r, ([-+]?\d+\.\d+(?:e[-+]?\d+)?)\)",
+                       body)
+    cs = [mp.mpf(float(c5))] + [mp.mpf(float(a or b)) for a, b in steps]
+    assert len(cs) == 4 and "__builtin_fma(q, r, 1.0)" in body
+    cs += [mp.mpf(1), mp.mpf(1)]  # q's constant term, then exp(r) = 1 + r q(r)
+    r1 = mp.log(2) / 128
+    worst = mp.mpf(0)
+    n = 4000
+    for i in range(n + 1):
+        x = -r1 + 2 * r1 * i / n
+        p = mp.mpf(0)
+        for c in cs:
+            p = p * x + c
+        worst = max(worst, abs(p / mp.exp(x) - 1))
+    assert worst <= 2.3e-18, float(worst)
+
+
+def test_exp_table_and_reduction_constants():
+    """The 64 entries of EXP2_J64 are 2^(j/64) rounded to nearest binary64, and
+    exp_f64's reduction constants are 64/ln2 rounded, and ln2/64 as a rounded
+    head plus its rounded remainder (Cody and Waite's split)."""
+    mp.mp.dps = 50
+    src, body = exp_f64_source()
+    tab = src[src.index("EXP2_J64[64] = {"):]
+    tab = tab[:tab.index("};")]
+    vals = [float.fromhex(x) for x in re.findall(r"0x[0-9a-f]\.[0-9a-f]+p[-+]\d+", tab)]
+    assert len(vals) == 64
+    for j, v in enumerate(vals):
+        assert v == float(mp.power(2, mp.mpf(j) / 64)), j
+    ln2_64 = mp.log(2) / 64
+    k = re.search(r"__builtin_fma\(e, ([\d.e+-]+), SHIFT\)", body).group(1)
+    hi, lo = re.findall(r"__builtin_fma\(-n, ([\d.e+-]+), (?:e|r)\)", body)
+    assert float(k) == float(1 / ln2_64)
+    assert float(hi) == float(ln2_64)
+    assert float(lo) == float(ln2_64 - mp.mpf(float(hi)))
