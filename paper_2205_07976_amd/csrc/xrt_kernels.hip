@@ -60,7 +60,7 @@ __device__ __forceinline__ void sample_dir(const Params &p, int i_f, int i_s, in
 // expm1 so that thin layers keep their relative accuracy.  The library's own
 // exp and expm1 (xrt_math.h) rather than the device libm's: those carry
 // special-case paths whose registers set the high-water mark of every kernel
-// that evaluates a sample point (113 against 73 VGPRs in the binary64 spots
+// that evaluates a sample point (115 against 75 VGPRs in the binary64 spots
 // kernel), for arguments that never occur here.
 __device__ __forceinline__ double sample_weight(const Params &p, const double d[3], double R, int t)
 {
@@ -1266,9 +1266,13 @@ hipError_t launch_serve(const ServeArgs &a, int precision, int shape, int n_wg, 
 //   dL/dscale    = sum g_p I_p / scale,
 // where h_i = M0_i . (Q^T S), Q = umat_m R_k, L2 = prod N_i^2
 // exp(-gk_i f_i^2) with gk_i = 2 N_i^2 / c, dL2/dh_i = -2 gk_i f_i L2 and
-// dL2/dN_i = (2/N_i) (1 - gk_i f_i^2) L2.  Each lane owns a pixel; the 13
-// sums are reduced over the workgroup by a fixed tree and then over the
-// workgroups by a fixed-order kernel, so the result is deterministic.
+// dL2/dN_i = (2/N_i) (1 - gk_i f_i^2) L2.  The factors -2 gk_i and 2/N_i
+// (and 1/scale) are the same for every term, so the term loops accumulate
+// the sums without them (f_i (Q^T S)_c B, (1 - gk_i f_i^2) B and B, with B
+// = g_p K w P dOmega C F^2 L2) and the final reduction applies them once.
+// Each lane owns a pixel; the 13 sums are reduced over the workgroup by a
+// fixed tree and then over the workgroups by a fixed-order kernel, so the
+// result is deterministic.
 // ---------------------------------------------------------------------------
 template <bool CLAMP>
 __device__ __forceinline__ void grad_term_f64(const Params &p, __amdgpu_buffer_rsrc_t tab, const double *Q,
@@ -1289,10 +1293,10 @@ __device__ __forceinline__ void grad_term_f64(const Params &p, __amdgpu_buffer_r
     const double base = w * load_f64(tab, table_offset<CLAMP>(p, hr, p.off64)) * exp_f64(e, c5);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        const double dh = base * p.m2gk[i] * f[i];
+        const double dh = base * f[i];
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[3 * i + c] = __builtin_fma(dh, Sp[c], acc[3 * i + c]);
-        acc[9 + i] = __builtin_fma(base * p.inv2N[i], __builtin_fma(-p.gk[i], f[i] * f[i], 1.0), acc[9 + i]);
+        acc[9 + i] = __builtin_fma(base, __builtin_fma(-p.gk[i], f[i] * f[i], 1.0), acc[9 + i]);
     }
     acc[12] += base;
 }
@@ -1336,11 +1340,10 @@ __device__ __forceinline__ void grad_add_mixed(const Params &p, const GradTerm &
     const float base = w * g.F2 * __expf(__builtin_fminf((float)(g.e - ref.m), GAUSS_REF_STEP));
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        const float dh = base * (float)p.m2gk[i] * g.f[i];
+        const float dh = base * g.f[i];
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[3 * i + c] = __builtin_fmaf(dh, g.Sf[c], acc[3 * i + c]);
-        acc[9 + i] = __builtin_fmaf(base * (float)p.inv2N[i],
-                                    __builtin_fmaf(-(float)p.gk[i], g.f[i] * g.f[i], 1.0f), acc[9 + i]);
+        acc[9 + i] = __builtin_fmaf(base, __builtin_fmaf(-(float)p.gk[i], g.f[i] * g.f[i], 1.0f), acc[9 + i]);
     }
     acc[12] += base;
 }
@@ -1439,17 +1442,24 @@ __global__ __launch_bounds__(BLOCK) void grad_kernel(const Params p, const void 
     }
 }
 
-// grad13[c] = sum over workgroups b of partial[b][c], in a fixed order: lane t
-// adds b = t, t + 256, ... sequentially, then the fixed block tree.
+// The constant factor of each gradient component: -2 gk_i for dL/dM0 row i,
+// 2/N_i for dL/dN_i, 1/scale for dL/dscale.
+struct GradScale {
+    double k[13];
+};
+
+// grad13[c] = k[c] times the sum over workgroups b of partial[b][c], in a
+// fixed order: lane t adds b = t, t + 256, ... sequentially, then the fixed
+// block tree.
 __global__ __launch_bounds__(BLOCK) void grad_reduce_kernel(const double *partial, int n_blocks, double *grad13,
-                                                            double inv_scale)
+                                                            const GradScale g)
 {
     __shared__ double lds[4];
     for (int c = 0; c < 13; ++c) {
         double v = 0.0;
         for (int b = threadIdx.x; b < n_blocks; b += BLOCK) v += partial[13 * (size_t)b + c];
         const double s = block_sum(v, lds);
-        if (threadIdx.x == 0) grad13[c] = c == 12 ? s * inv_scale : s;
+        if (threadIdx.x == 0) grad13[c] = s * g.k[c];
     }
 }
 
@@ -1472,7 +1482,13 @@ hipError_t launch_grad(const Params &p, int precision, bool clamp, const void *d
         launch_grad_one<XRT_MIXED>(p, clamp, dLdI, dLdI_f64, partial, stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(grad_reduce_kernel, dim3(1), dim3(BLOCK), 0, stream, partial, p.n_tiles, grad13, inv_scale);
+    GradScale g;
+    for (int i = 0; i < 3; ++i) {
+        for (int c = 0; c < 3; ++c) g.k[3 * i + c] = p.m2gk[i];
+        g.k[9 + i] = p.inv2N[i];
+    }
+    g.k[12] = inv_scale;
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3(1), dim3(BLOCK), 0, stream, partial, p.n_tiles, grad13, g);
     return hipGetLastError();
 }
 

@@ -141,6 +141,12 @@ __device__ const double EXP2_J64[64] = {
     0x1.ea4afa2a490dap+0, 0x1.efa1bee615a27p+0, 0x1.f50765b6e4540p+0, 0x1.fa7c1819e90d8p+0,
 };
 
+// The leading coefficient of exp_f64's polynomial.  A loop that evaluates
+// many exponentials passes a copy that the compiler cannot see through (the
+// first Horner step's other constant takes the one scalar operand), as with
+// SINPI_C6.
+constexpr double EXP_C5 = 0.008333324607332198;
+
 // exp(e) in binary64 for the Gaussian lattice factor, by Tang's table-driven
 // method: e = n ln2/64 + r with n the integer nearest e 64/ln2, so that
 // exp(e) = 2^k 2^(j/64) exp(r) for n = 64 k + j, 0 <= j < 64, |r| <= ln2/128.
@@ -156,11 +162,6 @@ __device__ const double EXP2_J64[64] = {
 // half from the last rounding, a few hundredths from the rest.  For e <= 709
 // (the lattice exponents are at most log(Na^2 Nb^2 Nc^2)); e is raised to
 // -1100 first, where the result is 0 either way, so |n| stays below 2^17.
-// The leading coefficient of exp_f64's polynomial.  A loop that evaluates
-// many exponentials passes a copy that the compiler cannot see through (the
-// first Horner step's other constant takes the one scalar operand), as with
-// SINPI_C6.
-constexpr double EXP_C5 = 0.008333324607332198;
 
 __device__ __forceinline__ double exp_f64(double e, double c5 = EXP_C5)
 {
