@@ -175,8 +175,8 @@ hipError_t launch_pad_table(const void *src, int src_f64, int32_t na, int32_t nb
                             int32_t pad, double F_default, double *F2_64, float *F2_32,
                             hipStream_t stream);
 // Adjoint: partial sums per tile into partial[n_tiles][13], then one
-// fixed-order reduction into grad13 that applies each component's constant
-// factor (-2 gk_i, 2/N_i, inv_scale).
+// fixed-order reduction into grad13 that applies the components' constant
+// factors (-2 gk_i, 2/N_i and gk_i, inv_scale).
 hipError_t launch_grad(const Params &p, int precision, bool clamp, const void *dLdI, int dLdI_f64,
                        double *partial, double *grad13, double inv_scale, hipStream_t stream);
 hipError_t launch_serve(const ServeArgs &a, int precision, int shape, int n_wg, hipStream_t stream);

@@ -1270,6 +1270,9 @@ hipError_t launch_serve(const ServeArgs &a, int precision, int shape, int n_wg, 
 // (and 1/scale) are the same for every term, so the term loops accumulate
 // the sums without them (f_i (Q^T S)_c B, (1 - gk_i f_i^2) B and B, with B
 // = g_p K w P dOmega C F^2 L2) and the final reduction applies them once.
+// The binary64 loop accumulates f_i^2 B in place of (1 - gk_i f_i^2) B, and
+// the reduction forms sum B - gk_i sum f_i^2 B (the difference can cancel,
+// which costs at most a few binary64 roundings of either sum).
 // Each lane owns a pixel; the 13 sums are reduced over the workgroup by a
 // fixed tree and then over the workgroups by a fixed-order kernel, so the
 // result is deterministic.
@@ -1296,7 +1299,7 @@ __device__ __forceinline__ void grad_term_f64(const Params &p, __amdgpu_buffer_r
         const double dh = base * f[i];
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[3 * i + c] = __builtin_fma(dh, Sp[c], acc[3 * i + c]);
-        acc[9 + i] = __builtin_fma(base, __builtin_fma(-p.gk[i], f[i] * f[i], 1.0), acc[9 + i]);
+        acc[9 + i] = __builtin_fma(base, f[i] * f[i], acc[9 + i]);
     }
     acc[12] += base;
 }
@@ -1442,24 +1445,31 @@ __global__ __launch_bounds__(BLOCK) void grad_kernel(const Params p, const void 
     }
 }
 
-// The constant factor of each gradient component: -2 gk_i for dL/dM0 row i,
-// 2/N_i for dL/dN_i, 1/scale for dL/dscale.
+// The gradient from the 13 sums s: grad[c] = k[c] s[c], and for the three
+// dL/dN_i also + kb[i] s[12] (binary64: k = -2 gk_i / N_i on the sum of
+// f_i^2 B, kb = 2/N_i; mixed: k = 2/N_i on the sum of (1 - gk_i f_i^2) B,
+// kb = 0).  k is -2 gk_i for dL/dM0 row i and 1/scale for dL/dscale.
 struct GradScale {
     double k[13];
+    double kb[3];
 };
 
-// grad13[c] = k[c] times the sum over workgroups b of partial[b][c], in a
-// fixed order: lane t adds b = t, t + 256, ... sequentially, then the fixed
-// block tree.
+// grad13 from the sums over workgroups b of partial[b][c], each in a fixed
+// order: lane t adds b = t, t + 256, ... sequentially, then the fixed block
+// tree.
 __global__ __launch_bounds__(BLOCK) void grad_reduce_kernel(const double *partial, int n_blocks, double *grad13,
                                                             const GradScale g)
 {
     __shared__ double lds[4];
+    double s[13];
     for (int c = 0; c < 13; ++c) {
         double v = 0.0;
         for (int b = threadIdx.x; b < n_blocks; b += BLOCK) v += partial[13 * (size_t)b + c];
-        const double s = block_sum(v, lds);
-        if (threadIdx.x == 0) grad13[c] = s * g.k[c];
+        s[c] = block_sum(v, lds);
+    }
+    if (threadIdx.x == 0) {
+        for (int c = 0; c < 13; ++c) grad13[c] = s[c] * g.k[c];
+        for (int i = 0; i < 3; ++i) grad13[9 + i] = __builtin_fma(g.kb[i], s[12], grad13[9 + i]);
     }
 }
 
@@ -1485,7 +1495,8 @@ hipError_t launch_grad(const Params &p, int precision, bool clamp, const void *d
     GradScale g;
     for (int i = 0; i < 3; ++i) {
         for (int c = 0; c < 3; ++c) g.k[3 * i + c] = p.m2gk[i];
-        g.k[9 + i] = p.inv2N[i];
+        g.k[9 + i] = precision == XRT_FP64 ? -p.gk[i] * p.inv2N[i] : p.inv2N[i];
+        g.kb[i] = precision == XRT_FP64 ? p.inv2N[i] : 0.0;
     }
     g.k[12] = inv_scale;
     hipLaunchKernelGGL(grad_reduce_kernel, dim3(1), dim3(BLOCK), 0, stream, partial, p.n_tiles, grad13, g);
